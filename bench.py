@@ -1,0 +1,226 @@
+"""Benchmark: the 2D single-grid suite on one MI355X.
+
+Workload (one "step"): the four 2D stencils of the single-grid suite, each run
+for T = 1000 steps on an 8192 x 8192 FP64 interior with a Dirichlet halo:
+5-point star r=1, 9-point box r=1, 13-point star r=3, 25-point box r=2;
+coefficients U[0,1) normalised to sum 1, inputs U[0,1) (seeded, synthetic).
+Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: GCells/s over the whole step (cell-updates per second),
+the roofline record of the dominant kernel, the per-stencil breakdown with the
+fraction of the temporally blocked roofline min(t_eff * B / 2S, F / 2k), and
+the CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--T 1000]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VALU_TFLOPS = 78.6
+FP32_VALU_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def copy_bandwidth(torch, nbytes=2 << 30, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes / time), GB/s."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e9
+
+
+def cpu_baseline(problems, fields, budget_s=15.0):
+    """Oracle on a bounded sample: every stencil of the suite on the full-size
+    grid for a few steps, sized from a one-step calibration."""
+    import oracle
+    threads = oracle.default_threads()
+    cal = []
+    for prob, u0 in zip(problems, fields):
+        t0 = time.perf_counter()
+        oracle.sweep(prob.coeffs, prob.spec.r, u0, 1, threads=threads)
+        cal.append(time.perf_counter() - t0)
+    per_step = sum(cal)
+    steps = max(1, int(budget_s / max(per_step, 1e-3)))
+    steps = min(steps, 50)
+    t0 = time.perf_counter()
+    updates = 0
+    for prob, u0 in zip(problems, fields):
+        oracle.sweep(prob.coeffs, prob.spec.r, u0, steps, threads=threads)
+        updates += prob.cells * steps
+    dt = time.perf_counter() - t0
+    return {
+        "value": updates / dt / 1e9,
+        "unit": "GCells/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"all {len(problems)} stencils of the suite on the full {problems[0].interior[0]}x"
+                  f"{problems[0].interior[1]} grid, {steps} steps each ({updates:.3e} updates, "
+                  f"{dt:.1f} s)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--T", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--depth", type=int, default=0, help="force a temporal depth (0 = plan)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2305_07390_amd import stencil, workloads
+
+    torch.cuda.set_device(0)
+    problems = workloads.suite_2d_problems(args.n, args.T)
+    log(f"bench: 2D suite {args.n}^2 T={args.T}, {len(problems)} stencils")
+    fields, xs, ys, plans = [], [], [], []
+    for prob in problems:
+        u0 = prob.field(np.float64)
+        fields.append(u0)
+        x = torch.from_numpy(u0).cuda()
+        xs.append(x)
+        ys.append(torch.empty_like(x))
+        plans.append(stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, prob.T,
+                                  depth=args.depth))
+        log(f"  {prob.spec.name}: {plans[-1].info}")
+    torch.cuda.synchronize()
+
+    B = copy_bandwidth(torch)
+    log(f"copy bandwidth {B:.0f} GB/s")
+
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        for j, (plan, x, y) in enumerate(zip(plans, xs, ys)):
+            if events is not None:
+                events[j][0].record(stream)
+            plan.execute(x, y, stream)
+            if events is not None:
+                events[j][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    per = [[0.0, 0] for _ in problems]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in problems]
+        step(ev)
+        torch.cuda.synchronize()
+        for j, (a, b) in enumerate(ev):
+            per[j][0] += a.elapsed_time(b) * 1e-3
+            per[j][1] += 1
+        log(f"  step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    updates_per_step = sum(p.updates for p in problems)
+    value = updates_per_step * args.steps / wall / 1e9
+    S = 8
+    breakdown = []
+    dominant = None
+    for prob, plan, (tsum, cnt) in zip(problems, plans, per):
+        t = tsum / cnt
+        info = plan.info
+        t_eff = prob.T / info["passes"]
+        gcells = prob.updates / t / 1e9
+        r_hbm = t_eff * B / (2 * S)
+        r_hbm_spec = t_eff * HBM_PEAK_GBS / (2 * S)
+        r_valu = FP64_VALU_TFLOPS * 1e3 / (2 * prob.spec.points)
+        per_launch = t / info["passes"]
+        bytes_per_launch = 2 * S * prob.cells
+        row = {
+            "stencil": prob.spec.name, "points": prob.spec.points, "depth": info["depth"],
+            "passes": info["passes"], "t_eff": round(t_eff, 3), "scheme": info["scheme_name"],
+            "tiles": info["tiles"], "seg_len": info["seg_len"], "ms": round(t * 1e3, 3),
+            "gcells_per_s": round(gcells, 2),
+            "roofline_gcells": round(min(r_hbm, r_valu), 1),
+            "fraction": round(gcells / min(r_hbm, r_valu), 4),
+            "fraction_spec_hbm": round(gcells / min(r_hbm_spec, r_valu), 4),
+            "avg_launch_us": round(per_launch * 1e6, 2),
+            "achieved_GBs": round(bytes_per_launch / per_launch / 1e9, 1),
+            "tflops": round(2 * prob.spec.points * prob.updates / t / 1e12, 2),
+        }
+        breakdown.append(row)
+        if dominant is None or t > dominant[0]:
+            dominant = (t, row, bytes_per_launch, per_launch)
+
+    _, drow, dbytes, dlaunch = dominant
+    achieved = dbytes / dlaunch / 1e9
+    result = {
+        "metric": "GCells/s (cell-updates per second), 2D single-grid suite",
+        "value": round(value, 2),
+        "unit": "GCells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"2D single-grid suite: {args.n}x{args.n} FP64 interior, T={args.T}, "
+                        "5pt star r1 + 9pt box r1 + 13pt star r3 + 25pt box r2, Dirichlet halo",
+            "grid": [args.n, args.n], "T": args.T, "stencils": [p.spec.name for p in problems],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"tb2d ({drow['stencil']}, depth {drow['depth']})",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+        },
+        "copy_bandwidth_GBs": round(B, 1),
+        "per_stencil": breakdown,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(problems, fields)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,137 @@
+/*
+ * stencil.h -- C ABI of the MI355X (gfx950) temporally blocked stencil engine.
+ *
+ * The operation (paper Section 2.1, Listings 1-3): T out-of-place Jacobi steps
+ *
+ *     U^s(i) = sum_{p in P} w_p * U^{s-1}(i + p),   s = 1..T,
+ *
+ * on a 2D or 3D grid whose halo of width r is a Dirichlet boundary held at its
+ * initial values. Temporal blocking (paper Sections 2.1.2-2.1.3, 3, 4) fuses
+ * several steps per pass over HBM; the result does not depend on the blocking.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Coefficients: `coeffs` is a host array of (2r+1)^ndim doubles, the dense
+ *   coefficient box, row-major, slowest offset first: offset (p_0..p_{d-1})
+ *   sits at index sum_j (p_j + r) * (2r+1)^(d-1-j). An entry that is exactly
+ *   0.0 is an absent point (no load, no term). The library copies the
+ *   coefficients; the caller may free them on return. Single-precision plans
+ *   round every coefficient to float (nearest even) once.
+ * Summation: each cell adds its terms in that dense-box order, starting from
+ *   +0.0, with one fused multiply-add per term.
+ * Arrays: `in` and `out` are device pointers (caller-owned, never freed or
+ *   retained) to contiguous padded arrays of extents n_j + 2r per dimension,
+ *   slowest first, x fastest, in the plan's dtype. `in` is never written.
+ *   `out` receives the whole padded grid: U^T on the interior and the halo
+ *   copied from `in`. `in` and `out` must not overlap.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream). All device
+ *   work is enqueued on it and the call returns after enqueueing.
+ * Errors: every function returns a stencil_status; nothing throws across the
+ *   ABI. Argument errors are detected before any device call.
+ *   stencil_last_error() returns a thread-local message for the last failure.
+ * Threading: plans are immutable after creation and may be shared between
+ *   threads; concurrent executions of one plan need distinct workspaces.
+ */
+#ifndef STENCIL_H
+#define STENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STENCIL_OK = 0,
+  STENCIL_ERR_INVALID = -1,     /* bad argument (null pointer, ndim, radius, T, extent, dtype) */
+  STENCIL_ERR_UNSUPPORTED = -2, /* valid request with no implementation */
+  STENCIL_ERR_ALIAS = -3,       /* in and out overlap */
+  STENCIL_ERR_NOMEM = -4,       /* device or host allocation failed */
+  STENCIL_ERR_DEVICE = -5,      /* a HIP call failed */
+  STENCIL_ERR_BUDGET = -6,      /* request exceeds a memory budget */
+  STENCIL_ERR_TIMEOUT = -7      /* a bounded device wait expired */
+} stencil_status;
+
+typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype;
+
+/* Interior extents, slowest first; ndim is 2 or 3 (n[2] ignored for 2D). */
+typedef struct {
+  int32_t ndim;
+  int64_t n[3];
+} stencil_shape;
+
+/* Optional tuning hint; zero fields mean "choose automatically".
+ * depth: time steps fused per pass over HBM (paper Section 6.2).
+ * tile[0]: rows per streamed segment (2D); tile[1..2] reserved.
+ * flags: STENCIL_FLAG_NAIVE forces one plain step per pass. */
+typedef struct {
+  int32_t tile[3];
+  int32_t depth;
+  int32_t flags;
+} stencil_tuning;
+
+#define STENCIL_FLAG_NAIVE 1
+
+/* Execution scheme chosen by a plan. */
+typedef enum {
+  STENCIL_SCHEME_COPY = 0,       /* T = 0: out := in */
+  STENCIL_SCHEME_NAIVE = 1,      /* one step per pass, no temporal blocking */
+  STENCIL_SCHEME_BLOCKED_2D = 2  /* overlapped wave tiles streamed along y (tb2d) */
+} stencil_scheme;
+
+/* Pattern classes of the coefficient box. */
+typedef enum { STENCIL_STAR = 0, STENCIL_BOX = 1, STENCIL_GENERAL = 2 } stencil_pattern;
+
+/* What a plan will do (for inspection, tests and benchmarks). */
+typedef struct {
+  int32_t scheme;        /* stencil_scheme */
+  int32_t pattern;       /* stencil_pattern */
+  int32_t points;        /* non-zero coefficients k */
+  int32_t depth;         /* steps per pass (largest pass) */
+  int64_t passes;        /* passes over HBM */
+  int32_t tiles;         /* wave tiles per pass (blocked schemes) */
+  int32_t strips;        /* column strips (2D blocked) */
+  int32_t seg_len;       /* rows per segment (2D blocked) */
+  int32_t cols_per_lane; /* columns held by one lane (2D blocked) */
+  int32_t grid, block;   /* launch shape of the main kernel */
+  int64_t cells;         /* interior cells */
+  int64_t padded_bytes;  /* bytes of one padded array */
+  int64_t workspace_bytes;
+} stencil_plan_info;
+
+typedef struct stencil_plan_s* stencil_plan_t;
+
+/* Build a plan (host only, no device memory is touched except to read the
+ * device's properties). `hint` may be NULL. On success *plan owns host memory
+ * released by stencil_plan_destroy. */
+stencil_status stencil_plan(stencil_plan_t* plan, const double* coeffs, int32_t radius,
+                            const stencil_shape* shape, stencil_dtype dtype, int64_t T,
+                            const stencil_tuning* hint);
+
+/* Bytes of device workspace stencil_execute needs (0 when none). */
+stencil_status stencil_plan_workspace(stencil_plan_t plan, size_t* bytes);
+
+/* Describe the plan's decisions. */
+stencil_status stencil_plan_describe(stencil_plan_t plan, stencil_plan_info* info);
+
+/* Run the plan: in -> out on `stream`, using `workspace` (device memory of at
+ * least stencil_plan_workspace bytes, may be NULL when that is 0, must not
+ * overlap in or out). */
+stencil_status stencil_execute(stencil_plan_t plan, const void* in, void* out, void* workspace,
+                               void* stream);
+
+stencil_status stencil_plan_destroy(stencil_plan_t plan);
+
+/* One-shot: plan, stream-ordered workspace allocation, execute, release. */
+stencil_status stencil_run(const double* coeffs, int32_t radius, const stencil_shape* shape,
+                           stencil_dtype dtype, int64_t T, const void* in, void* out, void* stream);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* stencil_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STENCIL_H */

@@ -1,0 +1,452 @@
+// Host runtime behind include/stencil.h: argument validation, pattern
+// classification, planning (scheme, temporal depth, tiles), the pass schedule
+// and kernel launches. Compiled with hipcc for gfx950.
+#include "../../include/stencil.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+
+using namespace stencil_impl;
+
+namespace {
+
+constexpr int64_t kLdsBudget = 64 * 1024;
+
+thread_local std::string g_last_error;
+
+stencil_status fail(stencil_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+stencil_status hip_fail(hipError_t e, const char* what) {
+  return fail(STENCIL_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct DeviceInfo {
+  int cus = 0;
+  bool ok = false;
+};
+
+DeviceInfo device_info() {
+  static std::mutex mu;
+  static std::vector<DeviceInfo> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DeviceInfo{};
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1);
+  if (!cache[dev].ok) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return DeviceInfo{};
+    cache[dev].cus = prop.multiProcessorCount;
+    cache[dev].ok = true;
+  }
+  return cache[dev];
+}
+
+}  // namespace
+
+struct stencil_plan_s {
+  int ndim = 0;
+  int r = 0;
+  int64_t n[3] = {1, 1, 1};    // interior extents, slowest first (3 entries used for 3D)
+  int64_t ext[3] = {1, 1, 1};  // padded extents padded to 3 axes (leading 1s for 2D)
+  int rad[3] = {0, 0, 0};      // halo width per padded axis
+  stencil_dtype dtype = STENCIL_F64;
+  int64_t T = 0;
+  std::vector<double> coeffs;  // dense box
+  int pattern = STENCIL_GENERAL;
+  int points = 0;
+  int scheme = STENCIL_SCHEME_NAIVE;
+  int depth = 1;
+  std::vector<int> pass_depth;  // depth of each pass
+  // 2D blocked geometry
+  int strips = 0, segs = 0, seg_len = 0, tiles = 0, hq_rows = 0;
+  int grid = 0, block = 0;
+  int64_t cells = 0;
+  int64_t padded_elems = 0;
+  size_t elem = 8;
+  size_t workspace = 0;
+  // plain kernel taps (offset, weight), dense-box order
+  std::vector<int64_t> tap_off;
+  std::vector<double> tap_w;
+};
+
+namespace {
+
+bool classify(int ndim, int r, const double* c, int* pattern, int* points) {
+  const int side = 2 * r + 1;
+  const int count = ndim == 2 ? side * side : side * side * side;
+  bool star_full = true, box_full = true, any = false;
+  int k = 0;
+  for (int idx = 0; idx < count; ++idx) {
+    int rem = idx, nz_axes = 0;
+    for (int d = 0; d < ndim; ++d) {
+      if (rem % side != r) ++nz_axes;
+      rem /= side;
+    }
+    const bool on_star = nz_axes <= 1;
+    const bool nz = c[idx] != 0.0;
+    if (!std::isfinite(c[idx])) return false;
+    if (nz) { ++k; any = true; }
+    if (on_star != nz) star_full = false;
+    if (!nz) box_full = false;
+  }
+  *points = k;
+  if (!any) *pattern = STENCIL_GENERAL;
+  else if (star_full) *pattern = STENCIL_STAR;
+  else if (box_full) *pattern = STENCIL_BOX;
+  else *pattern = STENCIL_GENERAL;
+  return true;
+}
+
+// Temporal depth chosen without tuning data: deep enough to move the bound off
+// HBM (paper Section 6.2) within the compiled variants.
+int default_depth_2d(int r, int pattern, int dtype) {
+  const int maxd = tb2d_max_depth(dtype, r, pattern);
+  int d;
+  if (pattern == STENCIL_STAR) d = r == 1 ? 10 : r == 2 ? 6 : r == 3 ? 4 : 3;
+  else d = r == 1 ? 6 : r == 2 ? 3 : 2;
+  return std::min(d, maxd);
+}
+
+void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
+  const int V = tb2d_cols_per_lane(p->dtype);
+  const int W = kWave * V;
+  const int HL = (depth * p->r + V - 1) / V;
+  const int64_t nx = p->n[2];
+  const int64_t Q = p->ext[1];
+  const int64_t side_valid = (int64_t)(kWave - HL) * V;
+  const int64_t mid_valid = (int64_t)(kWave - 2 * HL) * V;
+  int64_t n_int = 0;
+  if (nx > 2 * side_valid) n_int = (nx - 2 * side_valid + mid_valid - 1) / mid_valid;
+  p->strips = (int)(2 + n_int);
+  (void)W;
+  int seg;
+  if (seg_hint > 0) {
+    seg = seg_hint;
+  } else {
+    // one tile per SIMD: 4 waves per CU
+    const int64_t target = (int64_t)cus * 4;
+    int64_t nseg = std::max<int64_t>(1, (target + p->strips - 1) / p->strips);
+    seg = (int)((Q + nseg - 1) / nseg);
+    const int min_seg = std::max(16, 4 * depth * p->r);
+    if (seg < min_seg) seg = min_seg;
+  }
+  // keep a tile's byte offsets within 31 bits
+  const int64_t row_bytes = p->ext[2] * (int64_t)p->elem;
+  const int64_t max_rows = ((int64_t)1 << 31) / row_bytes - 2 * depth * p->r - 16;
+  if (seg > max_rows) seg = (int)std::max<int64_t>(1, max_rows);
+  // the per-wave LDS halo queue (4 waves x rows x 2r values) stays within 64 KB
+  const int64_t lds_rows = kLdsBudget / (4 * 2 * p->r * (int64_t)p->elem) - 2 * depth * p->r - 8;
+  if (seg > lds_rows) seg = (int)std::max<int64_t>(1, lds_rows);
+  if (seg > Q) seg = (int)Q;
+  p->seg_len = seg;
+  p->segs = (int)((Q + seg - 1) / seg);
+  p->tiles = p->strips * p->segs;
+  p->hq_rows = seg + 2 * depth * p->r + 8;
+  p->block = 256;
+  p->grid = (p->tiles + 3) / 4;
+}
+
+stencil_status validate(const double* coeffs, int32_t radius, const stencil_shape* shape,
+                        stencil_dtype dtype, int64_t T) {
+  if (!coeffs) return fail(STENCIL_ERR_INVALID, "coeffs is NULL");
+  if (!shape) return fail(STENCIL_ERR_INVALID, "shape is NULL");
+  if (shape->ndim != 2 && shape->ndim != 3)
+    return fail(STENCIL_ERR_INVALID, "ndim must be 2 or 3 (got %d)", shape->ndim);
+  if (radius < 0 || radius > kMaxR)
+    return fail(STENCIL_ERR_INVALID, "radius must be in [0, %d] (got %d)", kMaxR, radius);
+  if (T < 0) return fail(STENCIL_ERR_INVALID, "T must be >= 0 (got %lld)", (long long)T);
+  if (dtype != STENCIL_F32 && dtype != STENCIL_F64)
+    return fail(STENCIL_ERR_INVALID, "unknown dtype %d", (int)dtype);
+  for (int d = 0; d < shape->ndim; ++d) {
+    if (shape->n[d] < 1)
+      return fail(STENCIL_ERR_INVALID, "extent n[%d] must be >= 1 (got %lld)", d,
+                  (long long)shape->n[d]);
+    if (shape->n[d] > ((int64_t)1 << 30))
+      return fail(STENCIL_ERR_INVALID, "extent n[%d] too large", d);
+  }
+  return STENCIL_OK;
+}
+
+}  // namespace
+
+namespace {
+
+template <typename Real>
+stencil_status run_blocked_2d(const stencil_plan_s* p, const void* in, void* out, void* ws,
+                              hipStream_t stream) {
+  const size_t npass = p->pass_depth.size();
+  // the pass sequence alternates between two buffers and ends in `out`
+  void* bufs[2];
+  if (npass % 2 == 1) { bufs[0] = out; bufs[1] = ws; }
+  else { bufs[0] = ws; bufs[1] = out; }
+  // halo frame of every buffer a pass writes: copied once from `in`
+  hipError_t e = frame_copy_launch(p->dtype == STENCIL_F64 ? kF64 : kF32, in, out, p->ext, p->rad, stream);
+  if (e != hipSuccess) return hip_fail(e, "halo copy");
+  if (npass >= 2) {
+    e = frame_copy_launch(p->dtype == STENCIL_F64 ? kF64 : kF32, in, ws, p->ext, p->rad, stream);
+    if (e != hipSuccess) return hip_fail(e, "halo copy");
+  }
+  Tb2dParams<Real> prm;
+  std::memset(&prm, 0, sizeof(prm));
+  prm.orig = in;
+  prm.P = p->ext[2];
+  prm.Q = p->ext[1];
+  prm.n_strips = p->strips;
+  prm.n_segs = p->segs;
+  prm.seg_len = p->seg_len;
+  prm.ntiles = p->tiles;
+  prm.hq_rows = p->hq_rows;
+  for (size_t i = 0; i < p->coeffs.size(); ++i) prm.w[i] = (Real)p->coeffs[i];
+  const size_t lds = (size_t)4 * p->hq_rows * 2 * p->r * sizeof(Real);
+  const void* src = in;
+  for (size_t k = 0; k < npass; ++k) {
+    prm.src = src;
+    prm.dst = bufs[k % 2];
+    e = tb2d_launch(p->dtype == STENCIL_F64 ? kF64 : kF32, p->r, p->pattern, p->pass_depth[k], &prm,
+                    p->grid, p->block, lds, stream);
+    if (e != hipSuccess) return hip_fail(e, "blocked 2D pass launch");
+    src = bufs[k % 2];
+  }
+  return STENCIL_OK;
+}
+
+template <typename Real>
+stencil_status run_naive(const stencil_plan_s* p, const void* in, void* out, void* ws,
+                         hipStream_t stream) {
+  const size_t bytes = (size_t)p->padded_elems * p->elem;
+  const size_t npass = p->pass_depth.size();
+  void* work = npass >= 2 ? ws : nullptr;
+  hipError_t e = hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e, "copy in->out");
+  if (work) {
+    e = hipMemcpyAsync(work, in, bytes, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_fail(e, "copy in->workspace");
+  }
+  void* bufs[2];
+  if (npass % 2 == 1) { bufs[0] = out; bufs[1] = work; }
+  else { bufs[0] = work; bufs[1] = out; }
+  NaiveParams<Real> prm;
+  std::memset(&prm, 0, sizeof(prm));
+  for (int d = 0; d < 3; ++d) {
+    prm.ext[d] = p->ext[d];
+    prm.lo[d] = p->rad[d];
+    prm.hi[d] = (int32_t)(p->ext[d] - p->rad[d]);
+  }
+  prm.ntaps = (int32_t)p->tap_off.size();
+  for (size_t i = 0; i < p->tap_off.size(); ++i) {
+    prm.off[i] = p->tap_off[i];
+    prm.w[i] = (Real)p->tap_w[i];
+  }
+  const void* src = in;
+  for (size_t k = 0; k < npass; ++k) {
+    prm.src = src;
+    prm.dst = bufs[k % 2];
+    e = naive_launch(p->dtype == STENCIL_F64 ? kF64 : kF32, &prm, p->cells, stream);
+    if (e != hipSuccess) return hip_fail(e, "plain step launch");
+    src = bufs[k % 2];
+  }
+  return STENCIL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stencil_last_error(void) { return g_last_error.c_str(); }
+
+stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int32_t radius,
+                            const stencil_shape* shape, stencil_dtype dtype, int64_t T,
+                            const stencil_tuning* hint) {
+  if (!out_plan) return fail(STENCIL_ERR_INVALID, "plan is NULL");
+  *out_plan = nullptr;
+  stencil_status st = validate(coeffs, radius, shape, dtype, T);
+  if (st != STENCIL_OK) return st;
+
+  stencil_plan_s* p = new (std::nothrow) stencil_plan_s();
+  if (!p) return fail(STENCIL_ERR_NOMEM, "host allocation failed");
+  p->ndim = shape->ndim;
+  p->r = radius;
+  p->dtype = dtype;
+  p->T = T;
+  p->elem = dtype == STENCIL_F64 ? 8 : 4;
+  const int side = 2 * radius + 1;
+  const int count = p->ndim == 2 ? side * side : side * side * side;
+  p->coeffs.assign(coeffs, coeffs + count);
+  if (!classify(p->ndim, radius, coeffs, &p->pattern, &p->points)) {
+    delete p;
+    return fail(STENCIL_ERR_INVALID, "coefficients must be finite");
+  }
+  const int off = 3 - p->ndim;
+  p->cells = 1;
+  p->padded_elems = 1;
+  for (int d = 0; d < p->ndim; ++d) {
+    p->n[off + d] = shape->n[d];
+    p->ext[off + d] = shape->n[d] + 2 * radius;
+    p->rad[off + d] = radius;
+    p->cells *= shape->n[d];
+    p->padded_elems *= p->ext[off + d];
+  }
+  // taps for the plain kernel
+  for (int idx = 0; idx < count; ++idx) {
+    if (coeffs[idx] == 0.0) continue;
+    int rem = idx;
+    int64_t o = 0, stride = 1;
+    for (int d = 2; d >= off; --d) {
+      const int pd = rem % side - radius;
+      rem /= side;
+      o += (int64_t)pd * stride;
+      stride *= p->ext[d];
+    }
+    p->tap_off.push_back(o);
+    p->tap_w.push_back(coeffs[idx]);
+  }
+
+  const bool force_naive = hint && (hint->flags & STENCIL_FLAG_NAIVE);
+  if (T == 0) {
+    p->scheme = STENCIL_SCHEME_COPY;
+    p->depth = 0;
+  } else {
+    p->scheme = STENCIL_SCHEME_NAIVE;
+    p->depth = 1;
+    if (!force_naive && p->ndim == 2 && radius >= 1 && p->points > 0) {
+      const int V = tb2d_cols_per_lane(dtype);
+      const int maxd = tb2d_max_depth(dtype, radius, p->pattern);
+      int depth = (hint && hint->depth > 0) ? hint->depth : default_depth_2d(radius, p->pattern, dtype);
+      if (depth > maxd) depth = maxd;
+      if ((int64_t)depth > T) depth = (int)T;
+      // every strip must lie inside the interior, and its edge redundancy fit in the wave
+      const int HL = (depth * radius + V - 1) / V;
+      if (maxd >= 1 && depth >= 1 && p->n[2] >= (int64_t)kWave * V && 2 * HL < kWave) {
+        DeviceInfo di = device_info();
+        const int cus = di.ok ? di.cus : 256;
+        p->scheme = STENCIL_SCHEME_BLOCKED_2D;
+        p->depth = depth;
+        plan_2d_tiles(p, depth, hint ? hint->tile[0] : 0, cus);
+      }
+    }
+    if (p->scheme == STENCIL_SCHEME_BLOCKED_2D) {
+      int64_t q = T / p->depth, rem = T % p->depth;
+      p->pass_depth.assign((size_t)q, p->depth);
+      if (rem) p->pass_depth.push_back((int)rem);
+    } else {
+      p->pass_depth.assign((size_t)T, 1);
+    }
+  }
+  const size_t bytes = (size_t)p->padded_elems * p->elem;
+  p->workspace = p->pass_depth.size() >= 2 ? bytes : 0;
+  if (p->scheme == STENCIL_SCHEME_NAIVE && p->tap_off.size() > (size_t)kMaxNaiveTaps) {
+    delete p;
+    return fail(STENCIL_ERR_UNSUPPORTED, "more than %d non-zero coefficients without a blocked kernel",
+                kMaxNaiveTaps);
+  }
+  *out_plan = p;
+  return STENCIL_OK;
+}
+
+stencil_status stencil_plan_workspace(stencil_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  *bytes = plan->workspace;
+  return STENCIL_OK;
+}
+
+stencil_status stencil_plan_describe(stencil_plan_t plan, stencil_plan_info* info) {
+  if (!plan || !info) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->scheme = plan->scheme;
+  info->pattern = plan->pattern;
+  info->points = plan->points;
+  info->depth = plan->depth;
+  info->passes = (int64_t)plan->pass_depth.size();
+  info->tiles = plan->tiles;
+  info->strips = plan->strips;
+  info->seg_len = plan->seg_len;
+  info->cols_per_lane = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? tb2d_cols_per_lane(plan->dtype) : 1;
+  info->grid = plan->grid;
+  info->block = plan->block;
+  info->cells = plan->cells;
+  info->padded_bytes = plan->padded_elems * (int64_t)plan->elem;
+  info->workspace_bytes = (int64_t)plan->workspace;
+  return STENCIL_OK;
+}
+
+stencil_status stencil_plan_destroy(stencil_plan_t plan) {
+  delete plan;
+  return STENCIL_OK;
+}
+
+stencil_status stencil_execute(stencil_plan_t plan, const void* in, void* out, void* workspace,
+                               void* stream) {
+  if (!plan) return fail(STENCIL_ERR_INVALID, "plan is NULL");
+  if (!in || !out) return fail(STENCIL_ERR_INVALID, "in/out is NULL");
+  const size_t bytes = (size_t)plan->padded_elems * plan->elem;
+  const char* a = (const char*)in;
+  const char* b = (const char*)out;
+  if (a < b + bytes && b < a + bytes) return fail(STENCIL_ERR_ALIAS, "in and out overlap");
+  if (plan->workspace > 0) {
+    if (!workspace) return fail(STENCIL_ERR_INVALID, "workspace of %zu bytes required", plan->workspace);
+    const char* w = (const char*)workspace;
+    const size_t wb = plan->workspace;
+    if ((w < a + bytes && a < w + wb) || (w < b + bytes && b < w + wb))
+      return fail(STENCIL_ERR_ALIAS, "workspace overlaps in or out");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->scheme == STENCIL_SCHEME_COPY) {
+    hipError_t e = hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? STENCIL_OK : hip_fail(e, "copy");
+  }
+  if (plan->scheme == STENCIL_SCHEME_BLOCKED_2D) {
+    return plan->dtype == STENCIL_F64 ? run_blocked_2d<double>(plan, in, out, workspace, s)
+                                      : run_blocked_2d<float>(plan, in, out, workspace, s);
+  }
+  return plan->dtype == STENCIL_F64 ? run_naive<double>(plan, in, out, workspace, s)
+                                    : run_naive<float>(plan, in, out, workspace, s);
+}
+
+stencil_status stencil_run(const double* coeffs, int32_t radius, const stencil_shape* shape,
+                           stencil_dtype dtype, int64_t T, const void* in, void* out,
+                           void* stream) {
+  stencil_status st = validate(coeffs, radius, shape, dtype, T);
+  if (st != STENCIL_OK) return st;
+  if (!in || !out) return fail(STENCIL_ERR_INVALID, "in/out is NULL");
+  stencil_plan_t plan = nullptr;
+  st = stencil_plan(&plan, coeffs, radius, shape, dtype, T, nullptr);
+  if (st != STENCIL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = nullptr;
+  if (plan->workspace) {
+    hipError_t e = hipMallocAsync(&ws, plan->workspace, s);
+    if (e != hipSuccess) {
+      stencil_plan_destroy(plan);
+      return fail(STENCIL_ERR_NOMEM, "workspace allocation of %zu bytes failed: %s",
+                  plan->workspace, hipGetErrorString(e));
+    }
+  }
+  st = stencil_execute(plan, in, out, ws, stream);
+  if (ws) {
+    hipError_t e = hipFreeAsync(ws, s);
+    if (e != hipSuccess && st == STENCIL_OK) st = hip_fail(e, "workspace release");
+  }
+  stencil_plan_destroy(plan);
+  return st;
+}
+
+}  // extern "C"

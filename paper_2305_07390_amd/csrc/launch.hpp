@@ -1,0 +1,65 @@
+// Launch parameters shared by the host runtime (capi.cpp) and the HIP kernels.
+// Internal to the library: not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stencil_impl {
+
+enum ShapeClass : int { kStar = 0, kBox = 1, kGeneral = 2 };
+enum DType : int { kF32 = 0, kF64 = 1 };
+
+constexpr int kMaxR = 4;
+constexpr int kMaxBox2D = (2 * kMaxR + 1) * (2 * kMaxR + 1);
+constexpr int kMaxBox3D = (2 * kMaxR + 1) * (2 * kMaxR + 1) * (2 * kMaxR + 1);
+constexpr int kWave = 64;
+
+// One pass of the temporally blocked 2D kernel: DEPTH steps from src to dst.
+// Both arrays are padded (P columns x Q rows, x fastest). The grid is cut into
+// n_strips x n_segs wave tiles (see tb2d.hip for the geometry).
+// `orig` is the operation's original input (its halo is the Dirichlet data).
+// The interior columns r .. P-r-1 are cut into n_strips strips (at least two);
+// rows into n_segs segments of seg_len rows. Each wave keeps hq_rows x 2r
+// halo values in LDS.
+template <typename Real>
+struct Tb2dParams {
+  const void* src;
+  void* dst;
+  const void* orig;
+  int64_t P, Q;
+  int32_t n_strips, n_segs, seg_len, ntiles, hq_rows;
+  Real w[kMaxBox2D];  // dense (2r+1)^2 coefficient box, dense-box order
+};
+
+// One step of the plain kernel, any ndim <= 3 (padded extents ext[0..2],
+// slowest first; unused leading extents are 1 with zero halo). The non-zero
+// taps (linear offset, weight) are passed by value in dense-box order.
+constexpr int kMaxNaiveTaps = 128;
+template <typename Real>
+struct NaiveParams {
+  const void* src;
+  void* dst;
+  int64_t ext[3];
+  int32_t lo[3], hi[3];  // interior index range per axis
+  int32_t ntaps;
+  int64_t off[kMaxNaiveTaps];
+  Real w[kMaxNaiveTaps];
+};
+
+// Host entry points implemented in the .hip files.
+// Returns hipErrorInvalidValue when no kernel variant matches.
+hipError_t tb2d_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
+                       int block, size_t lds_bytes, hipStream_t stream);
+// Largest depth with a compiled variant (0 if none).
+int tb2d_max_depth(int dtype, int r, int shape);
+// Columns per lane for the given dtype.
+int tb2d_cols_per_lane(int dtype);
+
+hipError_t naive_launch(int dtype, const void* params, int64_t cells, hipStream_t stream);
+
+// Copy the halo frame (width r[j] on axis j; ext slowest first, unused leading
+// axes have extent 1 and width 0) from src to dst.
+hipError_t frame_copy_launch(int dtype, const void* src, void* dst, const int64_t ext[3],
+                             const int r[3], hipStream_t stream);
+
+}  // namespace stencil_impl

@@ -1,0 +1,7 @@
+// Compiled variants of the blocked 2D pass: f32, radius 2.
+#include "tb2d_impl.hpp"
+
+namespace stencil_impl {
+template hipError_t tb2d_launch_r<float, 2>(int, int, const Tb2dParams<float>*, int, int, size_t,
+                                            hipStream_t);
+}  // namespace stencil_impl

@@ -1,0 +1,399 @@
+// tb2d_impl.hpp -- temporally blocked 2D stencil pass for gfx950 (kernel templates).
+// Each tb2d_<dtype>_r<r>.hip translation unit instantiates one (dtype, radius)
+// so the variants compile in parallel.
+//
+// One pass advances a padded 2D grid by DEPTH Jacobi steps (paper Section 2.1)
+// with a single read and a single write of every cell in HBM, which is the
+// point of temporal blocking (paper Section 2.1.2 and Section 3).
+//
+// Decomposition (overlapped tiling, paper Sections 2.1.2-2.1.3 and 4.1 "SM
+// tiling", taken here to the granularity of one wavefront):
+//   * The grid is cut into vertical strips of W = 64*V columns; lane l of the
+//     wave owns the V consecutive columns X0 + l*V .. X0 + l*V + V - 1.
+//   * A strip is cut into row segments [Y0, Y1). The wave streams the segment
+//     top to bottom (N.5-D streaming along y), reading rows
+//     Y0 - DEPTH*r .. Y1 - 1 + DEPTH*r once from HBM.
+//   * The DEPTH time levels form a skewed wavefront: when input row y arrives,
+//     level s completes output row y - s*r. Each level keeps 2r partial-sum
+//     rows in registers; a newly arrived row is pushed into the partial sums of
+//     the 2r+1 output rows it touches (the paper's multi-queue, one queue per
+//     time level, Section 4.2, held in VGPRs with a compile-time rotation in
+//     place of the computed-address ring, since register arrays cannot be
+//     indexed at run time).
+//   * x-neighbours come from the adjacent lanes through DPP wave shifts; y
+//     neighbours are implicit in the streaming order. No LDS and no barrier:
+//     the waves of a workgroup are independent tiles.
+//   * Errors from the missing neighbours at the strip edges move inward by r
+//     columns per level, so an interior strip keeps HL = ceil(DEPTH*r/V) lanes
+//     of redundant work on each side (valid fraction of paper Section 5.2.1).
+//     A strip that touches the left or right edge of the grid needs no
+//     redundancy on that side: the Dirichlet halo never changes.
+//
+// Summation order: every output cell accumulates its terms in dense-box order
+// (rows dy = -r..r, within a row dx = -r..r), from +0.0, one fused
+// multiply-add per term. Rows of an output arrive in increasing dy, so the
+// push order reproduces exactly that order and results are bit-identical to
+// an unblocked sweep that uses the same order.
+//
+// Dirichlet halo (width r, held at its initial values): halo rows are detected
+// per wave (uniform branch) and take the value of their own row at the
+// previous level; halo columns exist only in the first and last strip, at
+// fixed register positions, and are patched by a per-lane select.
+//
+// Memory safety: loads and stores go through buffer descriptors limited to the
+// rows of the tile; out-of-range loads read zero and out-of-range stores are
+// dropped by the hardware.
+#pragma once
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace stencil_impl {
+using namespace stencil_dev;
+
+namespace {
+
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
+constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
+
+enum Edge { kInterior = 0, kLeftEdge = 1, kRightEdge = 2 };
+
+template <typename Real>
+struct ColsPerLane {
+  static constexpr int value = 32 / sizeof(Real);  // two 16-byte words per lane
+};
+
+template <int R>
+struct Ring0 {
+  // level-0 row slots: prefetch distance + 1, chosen so the rotation period
+  // lcm(2r, slots) stays short
+  static constexpr int value = (2 * R >= 4) ? 2 * R : 4;
+};
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+template <typename Real, int R, int SHAPE, int V>
+__device__ __forceinline__ void add_row(Real (&acc)[V], const Real (&x)[V],
+                                        const Real (&xe)[V + 2 * R], const Real* __restrict__ w,
+                                        int dy) {
+  constexpr int SIDE = 2 * R + 1;
+  if (SHAPE == kStar && dy != 0) {
+    const Real c = w[(dy + R) * SIDE + R];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = fma_t(c, x[v], acc[v]);
+  } else {
+#pragma unroll
+    for (int dx = -R; dx <= R; ++dx) {
+      const Real c = w[(dy + R) * SIDE + dx + R];
+      if (SHAPE == kGeneral && c == Real(0)) continue;
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = fma_t(c, xe[v + R + dx], acc[v]);
+    }
+  }
+}
+
+template <int CTRL, typename Real>
+__device__ __forceinline__ Real dpp_or(Real old, Real v);
+template <int CTRL>
+__device__ __forceinline__ double dpp_or(double old, double v) {
+  // lanes whose source lane does not exist keep `old`
+  unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  unsigned long long o = __builtin_bit_cast(unsigned long long, old);
+  int lo = __builtin_amdgcn_update_dpp((int)(unsigned)(o & 0xffffffffull),
+                                       (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL,
+                                       0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_or(float old, float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                               __builtin_bit_cast(int, v), CTRL,
+                                                               0xf, 0xf, false));
+}
+
+// Row x of V values per lane -> extended row with r neighbours on each side.
+// Lane 0 takes its left neighbours from `el` and lane 63 its right neighbours
+// from `er` (the Dirichlet halo of the row when the strip touches the grid's
+// edge; ignored otherwise); every other lane reads the adjacent lane.
+template <typename Real, int R, int V>
+__device__ __forceinline__ void extend_row(const Real (&x)[V], const Real (&el)[R],
+                                           const Real (&er)[R], Real (&xe)[V + 2 * R]) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) xe[R + v] = x[v];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    xe[j] = dpp_or<kDppWaveShr1>(el[j], x[V - R + j]);
+    xe[R + V + j] = dpp_or<kDppWaveShl1>(er[j], x[j]);
+  }
+}
+
+// Mutable per-tile streaming state (kept in registers after inlining).
+template <typename Real, int R, int DEPTH, int V>
+struct Tb2dState {
+  static constexpr int Z0 = Ring0<R>::value;
+  Real L0[Z0][V];          // level-0 rows in flight (prefetch ring)
+  Real A[DEPTH][2 * R][V]; // per level: partial sums of the 2r open output rows
+};
+
+// Per-tile constants.
+struct Tb2dTile {
+  __amdgpu_buffer_rsrc_t rs, rd;
+  uint32_t col_off, st_off, row_bytes;
+  int ys, Y0, Y1, Q, n_iter;
+  int lo[17];
+};
+
+// One streamed row (iteration i, phase ph of the unrolled loop).
+// GENERAL: warm-up/drain rows -- checks which levels hold valid rows and
+// handles the Dirichlet halo rows. Steady rows skip every check.
+template <typename Real, int R, int SHAPE, int DEPTH, int V, bool GENERAL>
+__device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const Tb2dTile& t,
+                                         const Real* __restrict__ w, const Real* hq, const int ph,
+                                         const int i) {
+  constexpr int R2 = 2 * R;
+  constexpr int Z0 = Ring0<R>::value;
+  constexpr int S = sizeof(Real);
+  {
+    const int ip = i + Z0 - 1;
+    if (!GENERAL || ip < t.n_iter)
+      load_vec<Real, V>(t.rs, t.col_off + (uint32_t)ip * t.row_bytes, 0, st.L0[(ph + Z0 - 1) % Z0]);
+  }
+  Real x[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) x[v] = st.L0[ph % Z0][v];
+  const int y = t.ys + i;
+  const int Q = t.Q;
+
+#pragma unroll
+  for (int s = 1; s <= DEPTH; ++s) {
+    const int u = y - (s - 1) * R;  // row of level s-1 arriving now
+    const bool ok = !GENERAL || ((u >= t.lo[s - 1]) && (u < Q));
+    // halo values of row u (two copies, so each DPP gets its own register)
+    Real el[R], er[R];
+    {
+      int hrow = u - t.ys;
+      if (GENERAL) hrow = hrow < 0 ? 0 : hrow;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        el[j] = hq[hrow * 2 * R + j];
+        er[j] = hq[hrow * 2 * R + R + j];
+      }
+    }
+    Real xe[V + 2 * R];
+    extend_row<Real, R, V>(x, el, er, xe);
+
+    // 1) the output completed by this arrival (dy = +r); it was started 2r
+    //    arrivals ago in the same slot
+    Real out[V];
+    {
+      const int o = u - R;
+      const int sl = ph % R2;
+      const bool halo_row = GENERAL && ((o < R) || (o >= Q - R));
+      if (ok && !halo_row) add_row<Real, R, SHAPE, V>(st.A[s - 1][sl], x, xe, w, R);
+#pragma unroll
+      for (int v = 0; v < V; ++v) out[v] = st.A[s - 1][sl][v];
+    }
+    // 2) open outputs (dy = r-1 .. -r+1) and the newly started one (dy = -r)
+    if (ok) {
+#pragma unroll
+      for (int dy = R - 1; dy >= -R; --dy) {
+        const int o = u - dy;
+        const int sl = pmod(ph - dy - R, R2);
+        const bool halo_row = GENERAL && ((o < R) || (o >= Q - R));
+        if (halo_row) {
+          if (dy == 0) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) st.A[s - 1][sl][v] = x[v];
+          }
+        } else {
+          if (dy == -R) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) st.A[s - 1][sl][v] = Real(0);
+          }
+          add_row<Real, R, SHAPE, V>(st.A[s - 1][sl], x, xe, w, dy);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) x[v] = out[v];
+  }
+  // level DEPTH completed row y - DEPTH*r
+  const int o = y - DEPTH * R;
+  if (!GENERAL || (o >= t.Y0 && o < t.Y1))
+    store_vec<Real, V>(t.rd, t.st_off + (uint32_t)(o - t.Y0) * t.row_bytes, 0, x);
+}
+
+template <typename Real, int R, int SHAPE, int DEPTH, int V>
+__device__ __forceinline__ void tb2d_tile(const Tb2dParams<Real>& a, Real* hq, const int lane,
+                                          const int edge, const int X0, const int la, const int lb,
+                                          const int Y0, const int Y1) {
+  constexpr int R2 = 2 * R;
+  constexpr int Z0 = Ring0<R>::value;
+  constexpr int UNROLL = lcm_c(R2, Z0);
+  constexpr int S = sizeof(Real);
+  const int P = (int)a.P;
+  const int Q = (int)a.Q;
+  const Real* __restrict__ w = a.w;
+
+  Tb2dTile t;
+  t.Q = Q;
+  t.Y0 = Y0;
+  t.Y1 = Y1;
+  t.ys = Y0 - DEPTH * R > 0 ? Y0 - DEPTH * R : 0;
+  const int ye = Y1 - 1 + DEPTH * R;
+  t.n_iter = ye - t.ys + 1;
+  int64_t src_range = (int64_t)(Q - t.ys) * P * S;
+  if (src_range > 0xffffffffll) src_range = 0xffffffffll;
+  t.rs = make_rsrc((const char*)a.src + (int64_t)t.ys * P * S, (uint32_t)src_range);
+  t.rd = make_rsrc((char*)a.dst + (int64_t)Y0 * P * S, (uint32_t)((int64_t)(Y1 - Y0) * P * S));
+  t.row_bytes = (uint32_t)(P * S);
+  t.col_off = (uint32_t)((X0 + lane * V) * S);
+  // lanes outside the store range get an offset past the descriptor: the
+  // hardware drops their stores
+  t.st_off = (lane >= la && lane < lb) ? t.col_off : 0x80000000u;
+  t.lo[0] = t.ys;
+#pragma unroll
+  for (int s = 1; s <= DEPTH; ++s) {
+    const int b = Y0 - (DEPTH - s) * R;
+    t.lo[s] = b > 0 ? b : 0;
+  }
+
+  // Edge strips: stage the Dirichlet halo columns of the tile's rows in LDS
+  // (left strip: columns 0..r-1, right strip: columns P-r..P-1), two copies
+  // per row.
+  if (edge != kInterior) {
+    const int c0 = edge == kLeftEdge ? 0 : P - R;
+    const int rows = (ye < Q - 1 ? ye : Q - 1) - t.ys + 1;
+    const __amdgpu_buffer_rsrc_t rin =
+        make_rsrc((const char*)a.orig + (int64_t)t.ys * P * S, (uint32_t)src_range);
+    for (int k = lane; k < rows * R; k += kWave) {
+      const int row = k / R, j = k - row * R;
+      const Real h = load_one<Real>(rin, (uint32_t)(row * P + c0 + j) * S, 0);
+      hq[row * 2 * R + j] = h;
+      hq[row * 2 * R + R + j] = h;
+    }
+  }
+
+  Tb2dState<Real, R, DEPTH, V> st;
+#pragma unroll
+  for (int z = 0; z < Z0; ++z)
+#pragma unroll
+    for (int v = 0; v < V; ++v) st.L0[z][v] = Real(0);
+#pragma unroll
+  for (int s = 0; s < DEPTH; ++s)
+#pragma unroll
+    for (int j = 0; j < R2; ++j)
+#pragma unroll
+      for (int v = 0; v < V; ++v) st.A[s][j][v] = Real(0);
+
+#pragma unroll
+  for (int p = 0; p < Z0 - 1; ++p)
+    if (p < t.n_iter) load_vec<Real, V>(t.rs, t.col_off + (uint32_t)p * t.row_bytes, 0, st.L0[p]);
+
+  // Steady rows: every level holds valid rows, no halo row is touched and the
+  // completed row is stored.
+  int y_a = t.lo[DEPTH - 1] + (DEPTH - 1) * R;
+  if (y_a < (DEPTH + 1) * R) y_a = (DEPTH + 1) * R;
+  if (y_a < Y0 + DEPTH * R) y_a = Y0 + DEPTH * R;
+  int y_b = Q - 2 * R;
+  if (y_b > ye + 1) y_b = ye + 1;
+  int i_a = y_a - t.ys;
+  i_a = (i_a + UNROLL - 1) / UNROLL * UNROLL;
+  int i_b = (y_b - t.ys) / UNROLL * UNROLL;
+  if (i_a > t.n_iter) i_a = (t.n_iter / UNROLL) * UNROLL;
+  if (i_b < i_a) i_b = i_a;
+
+  int base = 0;
+  for (; base < i_a; base += UNROLL) {
+#pragma unroll
+    for (int ph = 0; ph < UNROLL; ++ph)
+      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, true>(st, t, w, hq, ph, base + ph);
+  }
+  for (; base < i_b; base += UNROLL) {
+#pragma unroll
+    for (int ph = 0; ph < UNROLL; ++ph) tb2d_row<Real, R, SHAPE, DEPTH, V, false>(st, t, w, hq, ph, base + ph);
+  }
+  for (; base < t.n_iter; base += UNROLL) {
+#pragma unroll
+    for (int ph = 0; ph < UNROLL; ++ph)
+      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, true>(st, t, w, hq, ph, base + ph);
+  }
+}
+
+template <typename Real, int R, int SHAPE, int DEPTH>
+__global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
+  constexpr int V = ColsPerLane<Real>::value;
+  constexpr int HL = cdiv(DEPTH * R, V);
+  constexpr int W = kWave * V;
+  extern __shared__ char lds_raw[];
+  const int lane = lane_id();
+  const int waves = blockDim.x / kWave;
+  const int wid = uniform((int)(threadIdx.x / kWave));
+  Real* hq = (Real*)lds_raw + (size_t)wid * a.hq_rows * 2 * R;
+  const int stride = gridDim.x * waves;
+  const int ns = a.n_strips;
+  const int P = (int)a.P;
+  const int Q = (int)a.Q;
+  for (int tile = blockIdx.x * waves + wid; tile < a.ntiles; tile += stride) {
+    const int seg = tile / ns;
+    const int strip = tile - seg * ns;
+    const int Y0 = seg * a.seg_len;
+    const int Y1 = (Y0 + a.seg_len < Q) ? Y0 + a.seg_len : Q;
+    int edge, X0, la, lb;
+    if (strip == 0) {
+      edge = kLeftEdge; X0 = R; la = 0; lb = kWave - HL;
+    } else if (strip == ns - 1) {
+      edge = kRightEdge; X0 = P - R - W; la = HL; lb = kWave;
+    } else {
+      edge = kInterior;
+      X0 = R + (kWave - HL) * V + (strip - 1) * (kWave - 2 * HL) * V - HL * V;
+      la = HL; lb = kWave - HL;
+    }
+    tb2d_tile<Real, R, SHAPE, DEPTH, V>(a, hq, lane, edge, X0, la, lb, Y0, Y1);
+  }
+}
+
+// Deepest compiled variant per (radius, shape). Deeper levels cost registers:
+// each level holds 2r partial rows of V values per lane. The general pattern
+// (runtime zero skipping) is a fallback and stays shallow.
+constexpr int max_depth_c(int r, int shape) {
+  if (shape == kStar) return r == 1 ? 12 : r == 2 ? 8 : r == 3 ? 6 : 4;
+  if (shape == kBox) return r == 1 ? 8 : r == 2 ? 5 : r == 3 ? 3 : 2;
+  return r == 1 ? 3 : 2;
+}
+
+template <typename Real, int R, int SHAPE, int D>
+hipError_t launch_depth(int depth, const Tb2dParams<Real>* p, int grid, int block, size_t lds,
+                        hipStream_t s) {
+  if constexpr (D == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    if (depth == D) {
+      void* args[] = {(void*)p};
+      return hipLaunchKernel((const void*)&tb2d_kernel<Real, R, SHAPE, D>, dim3(grid), dim3(block),
+                             args, lds, s);
+    }
+    return launch_depth<Real, R, SHAPE, D - 1>(depth, p, grid, block, lds, s);
+  }
+}
+
+}  // namespace
+
+template <typename Real, int R>
+hipError_t tb2d_launch_r(int shape, int depth, const Tb2dParams<Real>* p, int grid, int block,
+                         size_t lds, hipStream_t s) {
+  switch (shape) {
+    case kStar:
+      return launch_depth<Real, R, kStar, max_depth_c(R, kStar)>(depth, p, grid, block, lds, s);
+    case kBox:
+      return launch_depth<Real, R, kBox, max_depth_c(R, kBox)>(depth, p, grid, block, lds, s);
+    case kGeneral:
+      return launch_depth<Real, R, kGeneral, max_depth_c(R, kGeneral)>(depth, p, grid, block, lds, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace stencil_impl

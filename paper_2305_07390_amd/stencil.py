@@ -1,0 +1,254 @@
+"""ctypes binding of ``libstencil.so`` (C ABI in ``include/stencil.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library. Functions keep the C names; ``Plan`` and ``run`` are
+thin conveniences over them for torch tensors (device memory and streams come
+from PyTorch). Importing this module does not load the library; the first call
+does, and raises ``StencilLibraryMissing`` when it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstencil.so")
+
+STENCIL_OK = 0
+STENCIL_ERR_INVALID = -1
+STENCIL_ERR_UNSUPPORTED = -2
+STENCIL_ERR_ALIAS = -3
+STENCIL_ERR_NOMEM = -4
+STENCIL_ERR_DEVICE = -5
+STENCIL_ERR_BUDGET = -6
+STENCIL_ERR_TIMEOUT = -7
+
+STENCIL_F32 = 0
+STENCIL_F64 = 1
+
+STENCIL_FLAG_NAIVE = 1
+
+SCHEME_NAMES = {0: "copy", 1: "naive", 2: "blocked_2d"}
+PATTERN_NAMES = {0: "star", 1: "box", 2: "general"}
+
+STATUS_NAMES = {
+    0: "STENCIL_OK", -1: "STENCIL_ERR_INVALID", -2: "STENCIL_ERR_UNSUPPORTED",
+    -3: "STENCIL_ERR_ALIAS", -4: "STENCIL_ERR_NOMEM", -5: "STENCIL_ERR_DEVICE",
+    -6: "STENCIL_ERR_BUDGET", -7: "STENCIL_ERR_TIMEOUT",
+}
+
+
+class StencilLibraryMissing(RuntimeError):
+    pass
+
+
+class StencilError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class stencil_shape(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int64 * 3)]
+
+
+class stencil_tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32 * 3), ("depth", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class stencil_plan_info(ctypes.Structure):
+    _fields_ = [
+        ("scheme", ctypes.c_int32), ("pattern", ctypes.c_int32), ("points", ctypes.c_int32),
+        ("depth", ctypes.c_int32), ("passes", ctypes.c_int64), ("tiles", ctypes.c_int32),
+        ("strips", ctypes.c_int32), ("seg_len", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32),
+        ("grid", ctypes.c_int32), ("block", ctypes.c_int32), ("cells", ctypes.c_int64),
+        ("padded_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["scheme_name"] = SCHEME_NAMES.get(self.scheme, str(self.scheme))
+        d["pattern_name"] = PATTERN_NAMES.get(self.pattern, str(self.pattern))
+        return d
+
+
+_P = ctypes.c_void_p
+_DBL = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes); the same names as include/stencil.h
+_SIGNATURES = {
+    "stencil_plan": (ctypes.c_int, [ctypes.POINTER(_P), _DBL, ctypes.c_int32,
+                                     ctypes.POINTER(stencil_shape), ctypes.c_int, ctypes.c_int64,
+                                     ctypes.POINTER(stencil_tuning)]),
+    "stencil_plan_workspace": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "stencil_plan_describe": (ctypes.c_int, [_P, ctypes.POINTER(stencil_plan_info)]),
+    "stencil_execute": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "stencil_plan_destroy": (ctypes.c_int, [_P]),
+    "stencil_run": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape),
+                                    ctypes.c_int, ctypes.c_int64, _P, _P, _P]),
+    "stencil_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises StencilLibraryMissing if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise StencilLibraryMissing(
+            f"{path} not found: build it with `python -m paper_2305_07390_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def stencil_last_error() -> str:
+    return load_library().stencil_last_error().decode()
+
+
+def _check(status: int):
+    if status != STENCIL_OK:
+        raise StencilError(status, stencil_last_error())
+
+
+def _shape(interior) -> stencil_shape:
+    s = stencil_shape()
+    s.ndim = len(interior)
+    for i, v in enumerate(interior[:3]):
+        s.n[i] = int(v)
+    return s
+
+
+def _coeff_ptr(coeffs: np.ndarray):
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    return c, c.ctypes.data_as(_DBL)
+
+
+def _dtype_code(dtype) -> int:
+    name = str(dtype)
+    if "float64" in name or name in ("f64", "double"):
+        return STENCIL_F64
+    if "float32" in name or name in ("f32", "float"):
+        return STENCIL_F32
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def stencil_plan(coeffs, radius: int, interior, dtype, T: int, depth: int = 0, seg_len: int = 0,
+                 flags: int = 0):
+    """Create a plan; returns an opaque handle (int). Raises StencilError."""
+    lib = load_library()
+    c, cp = _coeff_ptr(coeffs)
+    shp = _shape(interior)
+    tun = stencil_tuning()
+    tun.depth = int(depth)
+    tun.tile[0] = int(seg_len)
+    tun.flags = int(flags)
+    h = _P()
+    _check(lib.stencil_plan(ctypes.byref(h), cp, int(radius), ctypes.byref(shp), _dtype_code(dtype),
+                            int(T), ctypes.byref(tun)))
+    return h.value
+
+
+def stencil_plan_workspace(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(load_library().stencil_plan_workspace(plan, ctypes.byref(n)))
+    return n.value
+
+
+def stencil_plan_describe(plan) -> dict:
+    info = stencil_plan_info()
+    _check(load_library().stencil_plan_describe(plan, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def stencil_execute(plan, in_ptr: int, out_ptr: int, ws_ptr: int, stream: int = 0):
+    _check(load_library().stencil_execute(plan, in_ptr, out_ptr, ws_ptr or None, stream or None))
+
+
+def stencil_plan_destroy(plan):
+    _check(load_library().stencil_plan_destroy(plan))
+
+
+def stencil_run(coeffs, radius: int, interior, dtype, T: int, in_ptr: int, out_ptr: int,
+                stream: int = 0):
+    lib = load_library()
+    c, cp = _coeff_ptr(coeffs)
+    shp = _shape(interior)
+    _check(lib.stencil_run(cp, int(radius), ctypes.byref(shp), _dtype_code(dtype), int(T), in_ptr,
+                           out_ptr, stream or None))
+
+
+# --- torch conveniences -------------------------------------------------------
+
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def interior_of(x, radius: int):
+    return tuple(int(s) - 2 * radius for s in x.shape)
+
+
+class Plan:
+    """A plan bound to a coefficient box, radius, interior shape, dtype and T."""
+
+    def __init__(self, coeffs, radius, interior, dtype, T, depth=0, seg_len=0, flags=0):
+        self.handle = stencil_plan(coeffs, radius, interior, dtype, T, depth, seg_len, flags)
+        self.radius = radius
+        self.interior = tuple(interior)
+        self.T = T
+        self.info = stencil_plan_describe(self.handle)
+        self.workspace_bytes = stencil_plan_workspace(self.handle)
+        self._ws = None
+
+    def workspace(self, device):
+        import torch
+        if self.workspace_bytes == 0:
+            return None
+        if self._ws is None or self._ws.device != device:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+        return self._ws
+
+    def execute(self, x_in, x_out, stream=None):
+        """Run on torch device tensors (padded, contiguous). Enqueues on `stream`."""
+        if not (x_in.is_contiguous() and x_out.is_contiguous()):
+            raise ValueError("tensors must be contiguous")
+        ws = self.workspace(x_in.device)
+        stencil_execute(self.handle, x_in.data_ptr(), x_out.data_ptr(),
+                        ws.data_ptr() if ws is not None else 0, _stream_handle(stream))
+        return x_out
+
+    def close(self):
+        if self.handle:
+            stencil_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run(coeffs, radius: int, x_in, T: int, x_out=None, stream=None):
+    """One-shot stencil_run on torch device tensors; returns x_out."""
+    import torch
+    if x_out is None:
+        x_out = torch.empty_like(x_in)
+    stencil_run(coeffs, radius, interior_of(x_in, radius), x_in.dtype, T, x_in.data_ptr(),
+                x_out.data_ptr(), _stream_handle(stream))
+    return x_out

@@ -1,0 +1,48 @@
+"""Helpers for GPU tests: run the HIP path through the C ABI on numpy inputs
+and compare with the oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+from paper_2305_07390_amd import stencil as st
+
+
+def rel_err(got: np.ndarray, ref: np.ndarray, r: int) -> float:
+    """max over interior cells of |g - o| / max(|o|, 1e-6 max|o|)."""
+    core = tuple(slice(r, s - r) for s in ref.shape)
+    g = got[core].astype(np.float64)
+    o = ref[core].astype(np.float64)
+    if o.size == 0:
+        return 0.0
+    floor = 1e-6 * float(np.max(np.abs(o))) if np.any(o) else 1e-300
+    den = np.maximum(np.abs(o), floor)
+    return float(np.max(np.abs(g - o) / den))
+
+
+def halo_mask(shape, r):
+    m = np.ones(shape, dtype=bool)
+    m[tuple(slice(r, s - r) for s in shape)] = False
+    return m
+
+
+def gpu_sweep(coeffs, r, u0: np.ndarray, T: int, depth: int = 0, seg_len: int = 0, flags: int = 0,
+              repeats: int = 1, return_info: bool = False):
+    """Run the plan on the GPU; returns the result (and plan info). Checks that
+    the input tensor was not modified and that repeated runs are bitwise equal."""
+    import torch
+    interior = tuple(s - 2 * r for s in u0.shape)
+    x = torch.from_numpy(np.ascontiguousarray(u0)).cuda()
+    x_before = x.clone()
+    plan = st.Plan(coeffs, r, interior, u0.dtype, T, depth=depth, seg_len=seg_len, flags=flags)
+    outs = []
+    for _ in range(repeats):
+        y = torch.full_like(x, float("nan"))
+        plan.execute(x, y)
+        torch.cuda.synchronize()
+        outs.append(y.cpu().numpy())
+    assert torch.equal(x, x_before), "input array was modified"
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0], equal_nan=True), "repeated runs differ"
+    info = plan.info
+    plan.close()
+    return (outs[0], info) if return_info else outs[0]

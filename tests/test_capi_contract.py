@@ -1,0 +1,148 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol the header declares, and rejects bad arguments before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2305_07390_amd import stencil as st
+from paper_2305_07390_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stencil.h")
+
+
+def _lib():
+    try:
+        return st.load_library()
+    except st.StencilLibraryMissing:
+        pytest.skip("libstencil.so not built")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stencil_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = header_functions()
+    for required in ("stencil_plan", "stencil_execute", "stencil_run", "stencil_plan_destroy",
+                     "stencil_plan_workspace", "stencil_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    # the binding covers the same names
+    assert set(st.exported_symbols()) >= set(header_functions())
+
+
+def _plan_status(coeffs, r, interior, dtype, T):
+    lib = _lib()
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    shp = st._shape(interior)
+    h = ctypes.c_void_p()
+    status = lib.stencil_plan(ctypes.byref(h), c.ctypes.data_as(st._DBL), r, ctypes.byref(shp),
+                              dtype, T, None)
+    if status == st.STENCIL_OK:
+        lib.stencil_plan_destroy(h)
+    return status
+
+
+@pytest.mark.parametrize("case,expect", [
+    ("ndim1", st.STENCIL_ERR_INVALID),
+    ("ndim4", st.STENCIL_ERR_INVALID),
+    ("radius_neg", st.STENCIL_ERR_INVALID),
+    ("radius_5", st.STENCIL_ERR_INVALID),
+    ("T_neg", st.STENCIL_ERR_INVALID),
+    ("extent0", st.STENCIL_ERR_INVALID),
+    ("bad_dtype", st.STENCIL_ERR_INVALID),
+    ("nan_coeff", st.STENCIL_ERR_INVALID),
+    ("ok_2d", st.STENCIL_OK),
+    ("ok_3d", st.STENCIL_OK),
+    ("ok_T0", st.STENCIL_OK),
+    ("ok_r0", st.STENCIL_OK),
+])
+def test_plan_validation(case, expect):
+    w2 = wl.random_coeffs(2, "star", 1, 1)
+    w3 = wl.random_coeffs(3, "star", 1, 1)
+    args = {
+        "ndim1": (np.ones(3), 1, (5,), st.STENCIL_F64, 1),
+        "ndim4": (np.ones(81), 1, (3, 3, 3, 3), st.STENCIL_F64, 1),
+        "radius_neg": (w2, -1, (8, 8), st.STENCIL_F64, 1),
+        "radius_5": (np.ones((11, 11)), 5, (8, 8), st.STENCIL_F64, 1),
+        "T_neg": (w2, 1, (8, 8), st.STENCIL_F64, -1),
+        "extent0": (w2, 1, (0, 8), st.STENCIL_F64, 1),
+        "bad_dtype": (w2, 1, (8, 8), 7, 1),
+        "nan_coeff": (np.where(w2 > 0, np.nan, 0.0), 1, (8, 8), st.STENCIL_F64, 1),
+        "ok_2d": (w2, 1, (8, 8), st.STENCIL_F64, 3),
+        "ok_3d": (w3, 1, (4, 5, 6), st.STENCIL_F32, 3),
+        "ok_T0": (w2, 1, (8, 8), st.STENCIL_F64, 0),
+        "ok_r0": (np.array([[0.5]]), 0, (8, 8), st.STENCIL_F64, 2),
+    }[case]
+    assert _plan_status(*args) == expect, st.stencil_last_error()
+
+
+def test_null_pointers_rejected():
+    lib = _lib()
+    shp = st._shape((8, 8))
+    h = ctypes.c_void_p()
+    assert lib.stencil_plan(None, None, 1, ctypes.byref(shp), 1, 1, None) == st.STENCIL_ERR_INVALID
+    assert lib.stencil_plan(ctypes.byref(h), None, 1, ctypes.byref(shp), 1, 1, None) == st.STENCIL_ERR_INVALID
+    c = np.ones((3, 3))
+    assert lib.stencil_plan(ctypes.byref(h), c.ctypes.data_as(st._DBL), 1, None, 1, 1, None) == st.STENCIL_ERR_INVALID
+    assert "shape" in st.stencil_last_error()
+    assert lib.stencil_execute(None, None, None, None, None) == st.STENCIL_ERR_INVALID
+    assert lib.stencil_run(c.ctypes.data_as(st._DBL), 1, ctypes.byref(shp), 1, 1, None, None, None) == st.STENCIL_ERR_INVALID
+
+
+def test_alias_detected_before_device_work():
+    _lib()
+    w = wl.random_coeffs(2, "box", 1, 3)
+    plan = st.stencil_plan(w, 1, (300, 300), "float64", 10)
+    try:
+        info = st.stencil_plan_describe(plan)
+        nbytes = info["padded_bytes"]
+        fake = 1 << 40
+        ws = st.stencil_plan_workspace(plan)
+        with pytest.raises(st.StencilError) as e:
+            st.stencil_execute(plan, fake, fake + nbytes // 2, fake + 4 * nbytes, 0)
+        assert e.value.status == st.STENCIL_ERR_ALIAS
+        if ws:
+            with pytest.raises(st.StencilError) as e:
+                st.stencil_execute(plan, fake, fake + 2 * nbytes, fake + nbytes // 3, 0)
+            assert e.value.status == st.STENCIL_ERR_ALIAS
+            with pytest.raises(st.StencilError) as e:
+                st.stencil_execute(plan, fake, fake + 2 * nbytes, 0, 0)
+            assert e.value.status == st.STENCIL_ERR_INVALID
+    finally:
+        st.stencil_plan_destroy(plan)
+
+
+def test_plan_choices():
+    _lib()
+    # 2D 5-point on a wide grid: blocked scheme, passes = ceil(T / depth)
+    p = st.Plan(wl.uniform_5pt_coeffs(), 1, (1024, 2048), "float64", 1000)
+    i = p.info
+    assert i["scheme_name"] == "blocked_2d" and i["pattern_name"] == "star" and i["points"] == 5
+    assert i["passes"] == -(-1000 // i["depth"])
+    assert i["workspace_bytes"] == i["padded_bytes"]
+    # forced naive: one pass per step
+    q = st.Plan(wl.uniform_5pt_coeffs(), 1, (64, 64), "float64", 7, flags=st.STENCIL_FLAG_NAIVE)
+    assert q.info["scheme_name"] == "naive" and q.info["passes"] == 7
+    # T = 0 is a copy, no workspace
+    z = st.Plan(wl.uniform_5pt_coeffs(), 1, (64, 64), "float64", 0)
+    assert z.info["scheme_name"] == "copy" and z.workspace_bytes == 0
+    # a box pattern with a hole is classified general
+    w = wl.random_coeffs(2, "box", 1, 5)
+    w[0, 0] = 0.0
+    g = st.Plan(w, 1, (600, 600), "float32", 4)
+    assert g.info["pattern_name"] == "general" and g.info["points"] == 8
+    # a single pass needs no workspace
+    one = st.Plan(wl.uniform_5pt_coeffs(), 1, (600, 600), "float64", 3, depth=3)
+    assert one.info["passes"] == 1 and one.workspace_bytes == 0
