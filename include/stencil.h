@@ -94,6 +94,7 @@ typedef struct {
   int32_t strips;        /* column strips (2D blocked) */
   int32_t seg_len;       /* rows per segment (2D blocked) */
   int32_t cols_per_lane; /* columns held by one lane (2D blocked) */
+  int32_t redundant_lanes; /* lanes of overlap on each open strip side (2D blocked) */
   int32_t grid, block;   /* launch shape of the main kernel */
   int64_t cells;         /* interior cells */
   int64_t padded_bytes;  /* bytes of one padded array */

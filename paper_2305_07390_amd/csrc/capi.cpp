@@ -77,7 +77,7 @@ struct stencil_plan_s {
   int depth = 1;
   std::vector<int> pass_depth;  // depth of each pass
   // 2D blocked geometry
-  int strips = 0, segs = 0, seg_len = 0, tiles = 0, hq_rows = 0;
+  int strips = 0, segs = 0, seg_len = 0, tiles = 0, hq_rows = 0, hl = 0;
   int grid = 0, block = 0;
   int64_t cells = 0;
   int64_t padded_elems = 0;
@@ -137,6 +137,7 @@ void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
   int64_t n_int = 0;
   if (nx > 2 * side_valid) n_int = (nx - 2 * side_valid + mid_valid - 1) / mid_valid;
   p->strips = (int)(2 + n_int);
+  p->hl = HL;
   (void)W;
   int seg;
   if (seg_hint > 0) {
@@ -215,6 +216,7 @@ stencil_status run_blocked_2d(const stencil_plan_s* p, const void* in, void* out
   prm.seg_len = p->seg_len;
   prm.ntiles = p->tiles;
   prm.hq_rows = p->hq_rows;
+  prm.hl = p->hl;
   for (size_t i = 0; i < p->coeffs.size(); ++i) prm.w[i] = (Real)p->coeffs[i];
   const size_t lds = (size_t)4 * p->hq_rows * 2 * p->r * sizeof(Real);
   const void* src = in;
@@ -380,6 +382,7 @@ stencil_status stencil_plan_describe(stencil_plan_t plan, stencil_plan_info* inf
   info->strips = plan->strips;
   info->seg_len = plan->seg_len;
   info->cols_per_lane = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? tb2d_cols_per_lane(plan->dtype) : 1;
+  info->redundant_lanes = plan->hl;
   info->grid = plan->grid;
   info->block = plan->block;
   info->cells = plan->cells;

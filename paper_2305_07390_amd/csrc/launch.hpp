@@ -18,16 +18,17 @@ constexpr int kWave = 64;
 // Both arrays are padded (P columns x Q rows, x fastest). The grid is cut into
 // n_strips x n_segs wave tiles (see tb2d.hip for the geometry).
 // `orig` is the operation's original input (its halo is the Dirichlet data).
-// The interior columns r .. P-r-1 are cut into n_strips strips (at least two);
-// rows into n_segs segments of seg_len rows. Each wave keeps hq_rows x 2r
-// halo values in LDS.
+// The interior columns r .. P-r-1 are cut into n_strips strips (at least two)
+// laid out with hl redundant lanes on each open side (hl * V >= depth * r for
+// every pass of the plan); rows into n_segs segments of seg_len rows. Each wave
+// keeps hq_rows x 2r halo values in LDS.
 template <typename Real>
 struct Tb2dParams {
   const void* src;
   void* dst;
   const void* orig;
   int64_t P, Q;
-  int32_t n_strips, n_segs, seg_len, ntiles, hq_rows;
+  int32_t n_strips, n_segs, seg_len, ntiles, hq_rows, hl;
   Real w[kMaxBox2D];  // dense (2r+1)^2 coefficient box, dense-box order
 };
 

@@ -24,8 +24,10 @@
 //     neighbours are implicit in the streaming order. No LDS and no barrier:
 //     the waves of a workgroup are independent tiles.
 //   * Errors from the missing neighbours at the strip edges move inward by r
-//     columns per level, so an interior strip keeps HL = ceil(DEPTH*r/V) lanes
+//     columns per level, so an interior strip keeps HL >= ceil(DEPTH*r/V) lanes
 //     of redundant work on each side (valid fraction of paper Section 5.2.1).
+//     HL comes from the plan (the deepest pass), so that every pass of a plan
+//     uses the same strip layout and no interior strip reaches the halo.
 //     A strip that touches the left or right edge of the grid needs no
 //     redundancy on that side: the Dirichlet halo never changes.
 //
@@ -325,7 +327,6 @@ __device__ __forceinline__ void tb2d_tile(const Tb2dParams<Real>& a, Real* hq, c
 template <typename Real, int R, int SHAPE, int DEPTH>
 __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
   constexpr int V = ColsPerLane<Real>::value;
-  constexpr int HL = cdiv(DEPTH * R, V);
   constexpr int W = kWave * V;
   extern __shared__ char lds_raw[];
   const int lane = lane_id();
@@ -336,6 +337,8 @@ __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
   const int ns = a.n_strips;
   const int P = (int)a.P;
   const int Q = (int)a.Q;
+  // strip layout shared by every pass of the plan: hl * V >= DEPTH * r
+  const int HL = a.hl;
   for (int tile = blockIdx.x * waves + wid; tile < a.ntiles; tile += stride) {
     const int seg = tile / ns;
     const int strip = tile - seg * ns;

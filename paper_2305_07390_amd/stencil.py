@@ -63,6 +63,7 @@ class stencil_plan_info(ctypes.Structure):
         ("scheme", ctypes.c_int32), ("pattern", ctypes.c_int32), ("points", ctypes.c_int32),
         ("depth", ctypes.c_int32), ("passes", ctypes.c_int64), ("tiles", ctypes.c_int32),
         ("strips", ctypes.c_int32), ("seg_len", ctypes.c_int32), ("cols_per_lane", ctypes.c_int32),
+        ("redundant_lanes", ctypes.c_int32),
         ("grid", ctypes.c_int32), ("block", ctypes.c_int32), ("cells", ctypes.c_int64),
         ("padded_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
     ]

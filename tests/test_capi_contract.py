@@ -146,3 +146,46 @@ def test_plan_choices():
     # a single pass needs no workspace
     one = st.Plan(wl.uniform_5pt_coeffs(), 1, (600, 600), "float64", 3, depth=3)
     assert one.info["passes"] == 1 and one.workspace_bytes == 0
+
+
+def _strip_columns(P, R, V, HL, ns, strip):
+    """Mirror of the device strip layout: (loaded column range, stored column range)."""
+    W = 64 * V
+    if strip == 0:
+        X0, la, lb = R, 0, 64 - HL
+    elif strip == ns - 1:
+        X0, la, lb = P - R - W, HL, 64
+    else:
+        X0 = R + (64 - HL) * V + (strip - 1) * (64 - 2 * HL) * V - HL * V
+        la, lb = HL, 64 - HL
+    return (X0, X0 + W), (X0 + la * V, X0 + lb * V)
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("r,kind", [(1, "star"), (2, "box"), (3, "star"), (4, "star")])
+def test_strip_layout_covers_interior(dtype, r, kind):
+    """For every width and depth the planner accepts, the strips store every
+    interior column, load only interior columns, and keep at least depth*r
+    columns of redundancy on each open side."""
+    _lib()
+    w = wl.random_coeffs(2, kind, r, 9)
+    for nx in (256, 300, 511, 512, 513, 700, 1000, 1024, 1500, 3001, 8192):
+        for T in (1, 2, 3, 5, 8, 13):
+            try:
+                p = st.Plan(w, r, (40, nx), dtype, T)
+            except st.StencilError:
+                continue
+            i = p.info
+            if i["scheme_name"] != "blocked_2d":
+                continue
+            V, HL, ns = i["cols_per_lane"], i["redundant_lanes"], i["strips"]
+            assert HL * V >= i["depth"] * r
+            P = nx + 2 * r
+            covered = np.zeros(P, dtype=bool)
+            for sidx in range(ns):
+                (l0, l1), (s0, s1) = _strip_columns(P, r, V, HL, ns, sidx)
+                assert r <= l0 and l1 <= P - r, (nx, T, sidx, l0, l1)
+                if 0 < sidx < ns - 1:
+                    assert s0 - l0 >= i["depth"] * r and l1 - s1 >= i["depth"] * r
+                covered[s0:s1] = True
+            assert covered[r:P - r].all(), (nx, T)
