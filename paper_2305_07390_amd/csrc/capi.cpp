@@ -143,9 +143,11 @@ void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
   if (seg_hint > 0) {
     seg = seg_hint;
   } else {
-    // one tile per SIMD: 4 waves per CU
-    const int64_t target = (int64_t)cus * 4;
-    int64_t nseg = std::max<int64_t>(1, (target + p->strips - 1) / p->strips);
+    // One tile per SIMD (four waves per CU, one workgroup per CU): the tile
+    // count must not exceed the wave slots, or a second round of tiles
+    // doubles the pass time.
+    const int64_t slots = (int64_t)cus * 4;
+    int64_t nseg = std::max<int64_t>(1, slots / p->strips);
     seg = (int)((Q + nseg - 1) / nseg);
     const int min_seg = std::max(16, 4 * depth * p->r);
     if (seg < min_seg) seg = min_seg;
