@@ -137,3 +137,11 @@ def test_pins_hold_on_gpu():
     pins.check_constant(sweep, 2, "box", 2, T=9)
     pins.check_linear(sweep, 2, "star", 3, T=4)
     pins.check_composition(sweep, 2, "star", 1, T1=7, T2=12)
+
+
+def test_general_pattern_r3_plain_fallback():
+    w = wl.random_coeffs(2, "box", 3, 86)
+    w[1, 5] = 0.0
+    u0 = wl.make_field((120, 600), 3, 86)
+    info = _check(w, 3, u0, 3)
+    assert info["scheme_name"] == "naive" and info["pattern_name"] == "general"
