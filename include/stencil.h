@@ -63,7 +63,7 @@ typedef struct {
 
 /* Optional tuning hint; zero fields mean "choose automatically".
  * depth: time steps fused per pass over HBM (paper Section 6.2).
- * tile[0]: rows per streamed segment (2D); tile[1..2] reserved.
+ * tile[0]: rows (2D) or planes (3D) per streamed segment; tile[1..2] reserved.
  * flags: STENCIL_FLAG_NAIVE forces one plain step per pass. */
 typedef struct {
   int32_t tile[3];
@@ -77,7 +77,8 @@ typedef struct {
 typedef enum {
   STENCIL_SCHEME_COPY = 0,       /* T = 0: out := in */
   STENCIL_SCHEME_NAIVE = 1,      /* one step per pass, no temporal blocking */
-  STENCIL_SCHEME_BLOCKED_2D = 2  /* overlapped wave tiles streamed along y (tb2d) */
+  STENCIL_SCHEME_BLOCKED_2D = 2, /* overlapped wave tiles streamed along y (tb2d) */
+  STENCIL_SCHEME_BLOCKED_3D = 3  /* overlapped 64x64 workgroup tiles streamed along z (tb3d) */
 } stencil_scheme;
 
 /* Pattern classes of the coefficient box. */
@@ -91,10 +92,10 @@ typedef struct {
   int32_t depth;         /* steps per pass (largest pass) */
   int64_t passes;        /* passes over HBM */
   int32_t tiles;         /* wave tiles per pass (blocked schemes) */
-  int32_t strips;        /* column strips (2D blocked) */
-  int32_t seg_len;       /* rows per segment (2D blocked) */
-  int32_t cols_per_lane; /* columns held by one lane (2D blocked) */
-  int32_t redundant_lanes; /* lanes of overlap on each open strip side (2D blocked) */
+  int32_t strips;        /* column strips (2D) or xy tiles (3D) */
+  int32_t seg_len;       /* rows (2D) or planes (3D) per streamed segment */
+  int32_t cols_per_lane; /* x cells held by one lane */
+  int32_t redundant_lanes; /* lanes of overlap on each open tile side */
   int32_t grid, block;   /* launch shape of the main kernel */
   int64_t cells;         /* interior cells */
   int64_t padded_bytes;  /* bytes of one padded array */
@@ -127,6 +128,49 @@ stencil_status stencil_plan_destroy(stencil_plan_t plan);
 /* One-shot: plan, stream-ordered workspace allocation, execute, release. */
 stencil_status stencil_run(const double* coeffs, int32_t radius, const stencil_shape* shape,
                            stencil_dtype dtype, int64_t T, const void* in, void* out, void* stream);
+
+/* ---- Practical attainable performance model (paper Section 5, Section 6) ----
+ *
+ * Times of the three pressure points for one tile step of depth t:
+ *   T_gm  = a_gm * D_gm / B_gm * S          (global memory, Section 5.1)
+ *   T_sm  = a_sm * D_sm * t / B_sm * S      (on-chip memory; skipped if B_sm <= 0)
+ *   T_cmp = a_cmp * D_cmp * t / thr_cmp     (arithmetic)
+ * T_stencil = max of the three; P = D_all * t / T_stencil (cells/s); the valid
+ * proportion V is (tile - 2 t rad) / tile per tiled dimension for SM tiling
+ * (Section 5.2.1, both sides of a tile lose t*rad cells) and
+ * T_stencil / (T_stencil + n_sync * t_dsync) for device tiling (Section 5.2.2);
+ * PP = P * V. Also reported: the desired depth of Section 6.2 (smallest t that
+ * moves the bound off global memory; device tiling counts the tile halo in
+ * D_gm) and the minimum square device tile of Section 6.4. Units are the
+ * caller's, used consistently (bytes/s, flop/s, seconds, cells).
+ * Returns STENCIL_ERR_INVALID for NULL pointers or non-positive B_gm, thr_cmp,
+ * cell_bytes or t. */
+#define STENCIL_MODEL_NO_TILING 0
+#define STENCIL_MODEL_SM_TILING 1
+#define STENCIL_MODEL_DEVICE_TILING 2
+
+typedef struct {
+  double B_gm, B_sm, thr_cmp; /* bandwidths (bytes/s) and compute throughput (flop/s) */
+  double cell_bytes;          /* S */
+  double a_gm, a_sm, a_cmp;   /* accesses per cell (global, on-chip) and flops per cell */
+  double D_gm, D_sm, D_cmp, D_all; /* cells counted for each term and in P */
+  double t;                   /* temporal depth */
+  int32_t tiling;             /* STENCIL_MODEL_* */
+  int32_t tiled_dims;         /* dimensions with overlapped tiles (1 for 2D, 2 for 3D) */
+  double tile[2];             /* tile extents (cells) */
+  double rad;                 /* stencil radius */
+  double t_dsync;             /* seconds per device-wide synchronisation */
+  double n_sync;              /* synchronisations per tile step (1 with lazy streaming) */
+} stencil_model_params;
+
+typedef struct {
+  double T_gm, T_sm, T_cmp, T_stencil;
+  double P, V, PP;
+  double t_desired, min_tile;
+  int32_t bottleneck;         /* 0 global memory, 1 on-chip memory, 2 compute */
+} stencil_model_result;
+
+stencil_status stencil_model_eval(const stencil_model_params* params, stencil_model_result* result);
 
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* stencil_last_error(void);

@@ -78,6 +78,8 @@ struct stencil_plan_s {
   std::vector<int> pass_depth;  // depth of each pass
   // 2D blocked geometry
   int strips = 0, segs = 0, seg_len = 0, tiles = 0, hq_rows = 0, hl = 0;
+  // 3D blocked geometry
+  int sx = 0, sy = 0, hx = 0, hy = 0;
   int grid = 0, block = 0;
   int64_t cells = 0;
   int64_t padded_elems = 0;
@@ -86,6 +88,7 @@ struct stencil_plan_s {
   // plain kernel taps (offset, weight), dense-box order
   std::vector<int64_t> tap_off;
   std::vector<double> tap_w;
+  bool plan_ok_3d(int) const { return r <= 2; }
 };
 
 namespace {
@@ -170,6 +173,46 @@ void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
   p->grid = (p->tiles + 3) / 4;
 }
 
+// Temporal depth for the 3D pass: the deepest compiled variant (the pass is
+// HBM-bound at every depth the registers allow).
+int default_depth_3d(int r, int pattern, int dtype) { return tb3d_max_depth(dtype, r, pattern); }
+
+void plan_3d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
+  constexpr int B = 4, L = 16, T = L * B;
+  const int H = (depth * p->r + B - 1) / B;
+  auto strips = [&](int64_t n) {
+    const int64_t side = (int64_t)(L - H) * B, mid = (int64_t)(L - 2 * H) * B;
+    int64_t k = 0;
+    if (n > 2 * side) k = (n - 2 * side + mid - 1) / mid;
+    return (int)(2 + k);
+  };
+  p->hx = p->hy = H;
+  p->sx = strips(p->n[2]);
+  p->sy = strips(p->n[1]);
+  (void)T;
+  const int64_t Qz = p->ext[0];
+  const int64_t xy = (int64_t)p->sx * p->sy;
+  int seg;
+  if (seg_hint > 0) {
+    seg = seg_hint;
+  } else {
+    // one workgroup per CU (the LDS queues take most of a CU's 160 KB)
+    int64_t nseg = std::max<int64_t>(1, cus / xy);
+    seg = (int)((Qz + nseg - 1) / nseg);
+    const int min_seg = std::max(8, 4 * depth * p->r);
+    if (seg < min_seg) seg = min_seg;
+  }
+  const int64_t plane_bytes = p->ext[1] * p->ext[2] * (int64_t)p->elem;
+  const int64_t max_planes = ((int64_t)1 << 31) / plane_bytes - 2 * depth * p->r - 4;
+  if (seg > max_planes) seg = (int)std::max<int64_t>(1, max_planes);
+  if (seg > Qz) seg = (int)Qz;
+  p->seg_len = seg;
+  p->segs = (int)((Qz + seg - 1) / seg);
+  p->tiles = (int)(xy * p->segs);
+  p->block = 256;
+  p->grid = p->tiles;
+}
+
 stencil_status validate(const double* coeffs, int32_t radius, const stencil_shape* shape,
                         stencil_dtype dtype, int64_t T) {
   if (!coeffs) return fail(STENCIL_ERR_INVALID, "coeffs is NULL");
@@ -230,6 +273,44 @@ stencil_status run_blocked_2d(const stencil_plan_s* p, const void* in, void* out
     e = tb2d_launch(p->dtype == STENCIL_F64 ? kF64 : kF32, p->r, p->pattern, p->pass_depth[k], &prm,
                     p->grid, p->block, lds, stream);
     if (e != hipSuccess) return hip_fail(e, "blocked 2D pass launch");
+    src = bufs[k % 2];
+  }
+  return STENCIL_OK;
+}
+
+template <typename Real>
+stencil_status run_blocked_3d(const stencil_plan_s* p, const void* in, void* out, void* ws,
+                              hipStream_t stream) {
+  const size_t npass = p->pass_depth.size();
+  void* bufs[2];
+  if (npass % 2 == 1) { bufs[0] = out; bufs[1] = ws; }
+  else { bufs[0] = ws; bufs[1] = out; }
+  const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
+  hipError_t e = frame_copy_launch(dt, in, out, p->ext, p->rad, stream);
+  if (e != hipSuccess) return hip_fail(e, "halo copy");
+  if (npass >= 2) {
+    e = frame_copy_launch(dt, in, ws, p->ext, p->rad, stream);
+    if (e != hipSuccess) return hip_fail(e, "halo copy");
+  }
+  Tb3dParams<Real> prm;
+  std::memset(&prm, 0, sizeof(prm));
+  prm.P = p->ext[2];
+  prm.Qy = p->ext[1];
+  prm.Qz = p->ext[0];
+  prm.sx = p->sx;
+  prm.sy = p->sy;
+  prm.n_segs = p->segs;
+  prm.seg_len = p->seg_len;
+  prm.ntiles = p->tiles;
+  prm.hx = p->hx;
+  prm.hy = p->hy;
+  for (size_t i = 0; i < p->coeffs.size() && i < 125; ++i) prm.w[i] = (Real)p->coeffs[i];
+  const void* src = in;
+  for (size_t k = 0; k < npass; ++k) {
+    prm.src = src;
+    prm.dst = bufs[k % 2];
+    e = tb3d_launch(dt, p->r, p->pattern, p->pass_depth[k], &prm, p->grid, stream);
+    if (e != hipSuccess) return hip_fail(e, "blocked 3D pass launch");
     src = bufs[k % 2];
   }
   return STENCIL_OK;
@@ -349,7 +430,23 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
         plan_2d_tiles(p, depth, hint ? hint->tile[0] : 0, cus);
       }
     }
-    if (p->scheme == STENCIL_SCHEME_BLOCKED_2D) {
+    if (!force_naive && p->ndim == 3 && radius >= 1 && p->points > 0) {
+      const int maxd = tb3d_max_depth(dtype, radius, p->pattern);
+      int depth = (hint && hint->depth > 0) ? hint->depth : default_depth_3d(radius, p->pattern, dtype);
+      if (depth > maxd) depth = maxd;
+      if ((int64_t)depth > T) depth = (int)T;
+      const int H = (depth * radius + 3) / 4;
+      // tiles of 64 x 64 interior cells; each needs its redundant margins inside
+      if (maxd >= 1 && depth >= 1 && p->n[2] >= 64 && p->n[1] >= 64 && 2 * H < 16 &&
+          p->plan_ok_3d(depth)) {
+        DeviceInfo di = device_info();
+        const int cus = di.ok ? di.cus : 256;
+        p->scheme = STENCIL_SCHEME_BLOCKED_3D;
+        p->depth = depth;
+        plan_3d_tiles(p, depth, hint ? hint->tile[0] : 0, cus);
+      }
+    }
+    if (p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D) {
       int64_t q = T / p->depth, rem = T % p->depth;
       p->pass_depth.assign((size_t)q, p->depth);
       if (rem) p->pass_depth.push_back((int)rem);
@@ -385,8 +482,10 @@ stencil_status stencil_plan_describe(stencil_plan_t plan, stencil_plan_info* inf
   info->tiles = plan->tiles;
   info->strips = plan->strips;
   info->seg_len = plan->seg_len;
-  info->cols_per_lane = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? tb2d_cols_per_lane(plan->dtype) : 1;
-  info->redundant_lanes = plan->hl;
+  info->cols_per_lane = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? tb2d_cols_per_lane(plan->dtype)
+                        : plan->scheme == STENCIL_SCHEME_BLOCKED_3D ? 4 : 1;
+  info->redundant_lanes = plan->scheme == STENCIL_SCHEME_BLOCKED_3D ? plan->hx : plan->hl;
+  if (plan->scheme == STENCIL_SCHEME_BLOCKED_3D) info->strips = plan->sx * plan->sy;
   info->grid = plan->grid;
   info->block = plan->block;
   info->cells = plan->cells;
@@ -423,6 +522,10 @@ stencil_status stencil_execute(stencil_plan_t plan, const void* in, void* out, v
   if (plan->scheme == STENCIL_SCHEME_BLOCKED_2D) {
     return plan->dtype == STENCIL_F64 ? run_blocked_2d<double>(plan, in, out, workspace, s)
                                       : run_blocked_2d<float>(plan, in, out, workspace, s);
+  }
+  if (plan->scheme == STENCIL_SCHEME_BLOCKED_3D) {
+    return plan->dtype == STENCIL_F64 ? run_blocked_3d<double>(plan, in, out, workspace, s)
+                                      : run_blocked_3d<float>(plan, in, out, workspace, s);
   }
   return plan->dtype == STENCIL_F64 ? run_naive<double>(plan, in, out, workspace, s)
                                     : run_naive<float>(plan, in, out, workspace, s);

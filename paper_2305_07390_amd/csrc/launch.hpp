@@ -32,6 +32,19 @@ struct Tb2dParams {
   Real w[kMaxBox2D];  // dense (2r+1)^2 coefficient box, dense-box order
 };
 
+// One pass of the temporally blocked 3D kernel (tb3d_impl.hpp): padded extents
+// P (x), Qy, Qz; the interior xy plane is cut into sx x sy overlapped 64 x 64
+// tiles with hx / hy redundant lanes (4 cells each) per open side, z into
+// n_segs segments of seg_len planes; ntiles = sx * sy * n_segs workgroups.
+template <typename Real>
+struct Tb3dParams {
+  const void* src;
+  void* dst;
+  int64_t P, Qy, Qz;
+  int32_t sx, sy, n_segs, seg_len, ntiles, hx, hy;
+  Real w[kMaxBox3D > 125 ? 125 : kMaxBox3D];  // dense (2r+1)^3 box, r <= 2
+};
+
 // One step of the plain kernel, any ndim <= 3 (padded extents ext[0..2],
 // slowest first; unused leading extents are 1 with zero halo). The non-zero
 // taps (linear offset, weight) are passed by value in dense-box order.
@@ -57,6 +70,10 @@ int tb2d_max_depth(int dtype, int r, int shape);
 int tb2d_cols_per_lane(int dtype);
 
 hipError_t naive_launch(int dtype, const void* params, int64_t cells, hipStream_t stream);
+
+hipError_t tb3d_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
+                       hipStream_t stream);
+int tb3d_max_depth(int dtype, int r, int shape);
 
 // Copy the halo frame (width r[j] on axis j; ext slowest first, unused leading
 // axes have extent 1 and width 0) from src to dst.

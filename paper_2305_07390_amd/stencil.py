@@ -30,7 +30,7 @@ STENCIL_F64 = 1
 
 STENCIL_FLAG_NAIVE = 1
 
-SCHEME_NAMES = {0: "copy", 1: "naive", 2: "blocked_2d"}
+SCHEME_NAMES = {0: "copy", 1: "naive", 2: "blocked_2d", 3: "blocked_3d"}
 PATTERN_NAMES = {0: "star", 1: "box", 2: "general"}
 
 STATUS_NAMES = {
@@ -75,6 +75,25 @@ class stencil_plan_info(ctypes.Structure):
         return d
 
 
+class stencil_model_params(ctypes.Structure):
+    _fields_ = [("B_gm", ctypes.c_double), ("B_sm", ctypes.c_double), ("thr_cmp", ctypes.c_double),
+                ("cell_bytes", ctypes.c_double), ("a_gm", ctypes.c_double),
+                ("a_sm", ctypes.c_double), ("a_cmp", ctypes.c_double), ("D_gm", ctypes.c_double),
+                ("D_sm", ctypes.c_double), ("D_cmp", ctypes.c_double), ("D_all", ctypes.c_double),
+                ("t", ctypes.c_double), ("tiling", ctypes.c_int32), ("tiled_dims", ctypes.c_int32),
+                ("tile", ctypes.c_double * 2), ("rad", ctypes.c_double), ("t_dsync", ctypes.c_double),
+                ("n_sync", ctypes.c_double)]
+
+
+class stencil_model_result(ctypes.Structure):
+    _fields_ = [("T_gm", ctypes.c_double), ("T_sm", ctypes.c_double), ("T_cmp", ctypes.c_double),
+                ("T_stencil", ctypes.c_double), ("P", ctypes.c_double), ("V", ctypes.c_double),
+                ("PP", ctypes.c_double), ("t_desired", ctypes.c_double),
+                ("min_tile", ctypes.c_double), ("bottleneck", ctypes.c_int32)]
+
+
+MODEL_NO_TILING, MODEL_SM_TILING, MODEL_DEVICE_TILING = 0, 1, 2
+
 _P = ctypes.c_void_p
 _DBL = ctypes.POINTER(ctypes.c_double)
 
@@ -89,6 +108,8 @@ _SIGNATURES = {
     "stencil_plan_destroy": (ctypes.c_int, [_P]),
     "stencil_run": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape),
                                     ctypes.c_int, ctypes.c_int64, _P, _P, _P]),
+    "stencil_model_eval": (ctypes.c_int, [ctypes.POINTER(stencil_model_params),
+                                           ctypes.POINTER(stencil_model_result)]),
     "stencil_last_error": (ctypes.c_char_p, []),
 }
 
@@ -181,6 +202,20 @@ def stencil_execute(plan, in_ptr: int, out_ptr: int, ws_ptr: int, stream: int = 
 
 def stencil_plan_destroy(plan):
     _check(load_library().stencil_plan_destroy(plan))
+
+
+def stencil_model_eval(**kw) -> dict:
+    """Evaluate the attainable-performance model; keyword names as in the C struct
+    (``tile`` may be a pair)."""
+    p = stencil_model_params()
+    for k, v in kw.items():
+        if k == "tile":
+            p.tile[0], p.tile[1] = (list(v) + [0.0, 0.0])[:2]
+        else:
+            setattr(p, k, v)
+    r = stencil_model_result()
+    _check(load_library().stencil_model_eval(ctypes.byref(p), ctypes.byref(r)))
+    return {name: getattr(r, name) for name, _ in r._fields_}
 
 
 def stencil_run(coeffs, radius: int, interior, dtype, T: int, in_ptr: int, out_ptr: int,

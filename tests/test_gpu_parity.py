@@ -109,7 +109,7 @@ def test_r0_and_T0():
     assert np.array_equal(got, u1)
 
 
-def test_3d_plain():
+def test_3d_small_plain():
     for kind, r in (("star", 1), ("box", 1), ("star", 2)):
         w = wl.poisson_like_coeffs(3, kind, r, 84)
         u0 = wl.make_field((17, 23, 29), r, 84)
@@ -145,3 +145,41 @@ def test_general_pattern_r3_plain_fallback():
     u0 = wl.make_field((120, 600), 3, 86)
     info = _check(w, 3, u0, 3)
     assert info["scheme_name"] == "naive" and info["pattern_name"] == "general"
+
+
+# (name, kind, r, interior (z, y, x), T)
+CASES_3D = [
+    ("7pt_ragged_T1", "star", 1, (21, 70, 97), 1),
+    ("7pt_ragged_T2", "star", 1, (21, 70, 97), 2),
+    ("7pt_ragged_T5", "star", 1, (33, 131, 70), 5),
+    ("7pt_wide_T7", "star", 1, (17, 64, 200), 7),
+    ("27box_ragged_T3", "box", 1, (25, 90, 66), 3),
+    ("27box_T6", "box", 1, (19, 140, 77), 6),
+    ("13star_r2_T4", "star", 2, (20, 80, 90), 4),
+    ("7pt_thin_z_T4", "star", 1, (2, 70, 70), 4),
+]
+
+
+@pytest.mark.parametrize("name,kind,r,interior,T", CASES_3D, ids=[c[0] for c in CASES_3D])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_parity_3d(name, kind, r, interior, T, dtype):
+    seed = abs(hash(name)) % 1000
+    w = wl.poisson_like_coeffs(3, kind, r, seed)
+    u0 = wl.make_field(interior, r, seed, dtype)
+    _check(w, r, u0, T)
+
+
+@pytest.mark.parametrize("seg", [8, 13, 40])
+def test_3d_segment_invariance(seg):
+    w = wl.random_coeffs(3, "star", 1, 87)
+    u0 = wl.make_field((45, 75, 80), 1, 87)
+    info = _check(w, 1, u0, 5, seg_len=seg)
+    assert info["scheme_name"] == "blocked_3d"
+
+
+def test_3d_general_pattern():
+    w = wl.random_coeffs(3, "box", 1, 88)
+    w[0, 0, 0] = 0.0
+    u0 = wl.make_field((12, 70, 70), 1, 88)
+    info = _check(w, 1, u0, 3)
+    assert info["pattern_name"] == "general"
