@@ -129,6 +129,45 @@ stencil_status stencil_plan_destroy(stencil_plan_t plan);
 stencil_status stencil_run(const double* coeffs, int32_t radius, const stencil_shape* shape,
                            stencil_dtype dtype, int64_t T, const void* in, void* out, void* stream);
 
+/* ---- Batched execution (many independent grids in persistent launches) ----
+ *
+ * A job is one stencil_run request: coefficients (host, copied at submit),
+ * radius, interior shape, dtype, T, device arrays in / out (same conventions
+ * as stencil_run; `in` never written, `out` receives the padded result), a
+ * caller tag, and an optional depth hint (0 = planner's choice).
+ * stencil_batch_submit validates and plans every job (per_job_status[i] gets
+ * the job's status; invalid jobs are skipped), checks that no two jobs share
+ * memory, and enqueues on `stream`: one halo-frame copy launch, then one
+ * persistent launch per kernel variant in use, whose workgroups pull
+ * (job, pass, tile) items from a shared work list; a tile waits until its
+ * job's previous pass is complete (paper Section 4.1, tile-by-tile execution,
+ * applied across grids). Jobs without a blocked variant run with the plain
+ * kernel on the same stream. Workspace and control memory are allocated and
+ * released stream-ordered. Returns STENCIL_OK if at least the valid jobs were
+ * enqueued, STENCIL_ERR_INVALID if no job is valid or an argument is NULL,
+ * STENCIL_ERR_ALIAS if jobs overlap. A bounded device wait that expires is
+ * reported by the next stencil_sync on that stream. */
+typedef struct {
+  const double* coeffs;
+  int32_t radius;
+  stencil_shape shape;
+  stencil_dtype dtype;
+  int64_t T;
+  const void* in;
+  void* out;
+  uint64_t tag;
+  int32_t depth; /* 0: planner's choice */
+} stencil_job;
+
+stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* stream,
+                                    stencil_status* per_job_status);
+
+/* Wait for `stream` and report device-side failures of the library's kernels
+ * since the last call: STENCIL_ERR_TIMEOUT if a bounded wait expired (the
+ * affected results are undefined), STENCIL_ERR_DEVICE if the stream reports an
+ * error, else STENCIL_OK. */
+stencil_status stencil_sync(void* stream);
+
 /* ---- Practical attainable performance model (paper Section 5, Section 6) ----
  *
  * Times of the three pressure points for one tile step of depth t:

@@ -1,0 +1,246 @@
+// batch_impl.hpp -- persistent batch kernels over many independent grids.
+//
+// The decomposition of each grid is the single-grid one (tb2d / tb3d tiles);
+// what changes is the schedule (the paper's tile-by-tile execution, Section
+// 4.1, extended to a work list): a fixed set of workgroups pulls (job, pass,
+// tile) items from one counter, waits until the job's previous pass is
+// complete, runs the tile and publishes its completion. Waits are bounded by
+// a realtime-clock watchdog; an expired wait sets an error word, and every
+// later item of the launch skips its work so the launch still drains.
+#pragma once
+#include "tb2d_impl.hpp"
+#include "tb3d_impl.hpp"
+
+// Host launchers, one translation unit per (dimension, dtype); see batch*.hip.
+
+namespace stencil_impl {
+namespace batch {
+
+// Job descriptors live in global memory; their fields are the same for every
+// lane, so they are moved to scalar registers once per item (the kernel's own
+// stores could alias the descriptor as far as the compiler knows, which would
+// otherwise keep per-lane copies of every coefficient in VGPRs).
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)v & 0xffffffffull));
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double uni(double v) {
+  return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, v)));
+}
+__device__ __forceinline__ float uni(float v) {
+  return __builtin_bit_cast(float, uni(__builtin_bit_cast(int, v)));
+}
+template <typename T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+  return (T*)(uintptr_t)uni((int64_t)(uintptr_t)p);
+}
+
+// Chunk holding item `it`: the largest c with chunk_first[c] <= it.
+__device__ __forceinline__ int find_chunk(const BatchQueue& q, int64_t it) {
+  int lo = 0, hi = q.nchunks;  // chunk_first[lo] <= it < chunk_first[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (q.chunk_first[mid] <= it) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Wait until *ctr >= need. Returns false if the watchdog expired here or an
+// earlier wait of the launch already failed.
+__device__ __forceinline__ bool wait_count(const BatchQueue& q, const unsigned* ctr, unsigned need) {
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  while (true) {
+    const unsigned v = __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (v >= need) return true;
+    if (__hip_atomic_load(q.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+    if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > q.timeout_ticks) {
+      __hip_atomic_store(q.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+}
+
+// Pass k writes `out` when (npass - 1 - k) is even, else the workspace, so the
+// last pass writes `out`; pass 0 reads `in`.
+__device__ __forceinline__ void pass_buffers(const void* in, void* out, void* ws, int npass, int pass,
+                                             const void** src, void** dst) {
+  void* prev = ((npass - pass) & 1) == 0 ? out : ws;  // buffer of pass - 1
+  *src = pass == 0 ? in : (const void*)prev;
+  *dst = ((npass - 1 - pass) & 1) == 0 ? out : ws;
+}
+
+template <typename Real, int R, int SHAPE, int DEPTH>
+__global__ __launch_bounds__(256) void tb2d_batch_kernel(const Batch2DParams<Real> p) {
+  constexpr int V = ColsPerLane<Real>::value;
+  constexpr int W = kWave * V;
+  constexpr int KB = (2 * R + 1) * (2 * R + 1);
+  extern __shared__ char lds_raw[];
+  const int lane = lane_id();
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  Real* hq = (Real*)lds_raw + (size_t)wid * p.hq_rows * 2 * R;
+  const BatchQueue& q = p.q;
+  while (true) {
+    unsigned long long it = 0;
+    if (lane == 0) it = atomicAdd(q.cursor, 1ull);
+    const unsigned lo32 = __builtin_amdgcn_readfirstlane((unsigned)(it & 0xffffffffull));
+    const unsigned hi32 = __builtin_amdgcn_readfirstlane((unsigned)(it >> 32));
+    const int64_t item = (int64_t)(((unsigned long long)hi32 << 32) | lo32);
+    if (item >= q.nitems) break;
+    const int c = find_chunk(q, item);
+    const int job = uni(q.chunk_job[c]);
+    const int pass = uni(q.chunk_pass[c]);
+    const int tile = (int)(item - uni(q.chunk_first[c]));
+    const BatchJob2D<Real>& J = p.jobs[job];
+    const int tiles = uni(J.tiles);
+    bool ok = true;
+    if (pass > 0) ok = wait_count(q, q.done + job, (unsigned)pass * (unsigned)tiles);
+    if (ok) {
+      Real wl[KB];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) wl[k] = uni(J.w[k]);
+      const void* in = uni_ptr(J.in);
+      const int npass = uni(J.npass);
+      const void* src;
+      void* dst;
+      pass_buffers(in, uni_ptr(J.out), uni_ptr(J.ws), npass, pass, &src, &dst);
+      const int d = pass == npass - 1 ? uni(J.depth_last) : uni(J.depth);
+      const int P = (int)uni(J.P), Q = (int)uni(J.Q);
+      const int ns = uni(J.strips), HL = uni(J.hl), seg_len = uni(J.seg_len);
+      const int seg = tile / ns;
+      const int strip = tile - seg * ns;
+      const int Y0 = seg * seg_len;
+      const int Y1 = (Y0 + seg_len < Q) ? Y0 + seg_len : Q;
+      int edge, X0, la, lb;
+      if (ns == 1) {
+        edge = kBothEdges; X0 = R; la = 0; lb = kWave;
+      } else if (strip == 0) {
+        edge = kLeftEdge; X0 = R; la = 0; lb = kWave - HL;
+      } else if (strip == ns - 1) {
+        edge = kRightEdge; X0 = P - R - W; la = HL; lb = kWave;
+      } else {
+        edge = kInterior;
+        X0 = R + (kWave - HL) * V + (strip - 1) * (kWave - 2 * HL) * V - HL * V;
+        la = HL; lb = kWave - HL;
+      }
+      tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0,
+                                          Y1, d);
+    }
+    // publish: the release orders this wave's stores before the count
+    if (lane == 0) __hip_atomic_fetch_add(q.done + job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename Real, int R, int SHAPE, int DEPTH>
+__global__ __launch_bounds__(tb3d::kThreads) void tb3d_batch_kernel(const Batch3DParams<Real> p) {
+  using namespace tb3d;
+  using FL = FaceLayout<R>;
+  constexpr int KB = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+  extern __shared__ char lds_raw[];
+  Real* faces = (Real*)lds_raw;
+  Real* xchg = faces + kRing * FL::kPerPlane;
+  __shared__ long long s_item;
+  __shared__ int s_ok;
+  const BatchQueue& q = p.q;
+  while (true) {
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(q.cursor, 1ull);
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= q.nitems) break;
+    const int c = find_chunk(q, item);
+    const int job = uni(q.chunk_job[c]);
+    const int pass = uni(q.chunk_pass[c]);
+    const int tile = (int)(item - uni(q.chunk_first[c]));
+    const BatchJob3D<Real>& J = p.jobs[job];
+    const int tiles = uni(J.tiles);
+    if (threadIdx.x == 0) s_ok = pass > 0 ? (int)wait_count(q, q.done + job, (unsigned)pass * (unsigned)tiles) : 1;
+    __syncthreads();
+    const bool ok = s_ok != 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave sees the previous pass
+    if (ok) {
+      Real wl[KB];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) wl[k] = uni(J.w[k]);
+      const int npass = uni(J.npass);
+      const void* src;
+      void* dst;
+      pass_buffers(uni_ptr(J.in), uni_ptr(J.out), uni_ptr(J.ws), npass, pass, &src, &dst);
+      const int d = pass == npass - 1 ? uni(J.depth_last) : uni(J.depth);
+      const int P = (int)uni(J.P), Qy = (int)uni(J.Qy), Qz = (int)uni(J.Qz);
+      const int sx = uni(J.sx), sy = uni(J.sy), seg_len = uni(J.seg_len);
+      const int seg = tile / (sx * sy);
+      const int rem = tile - seg * sx * sy;
+      const int ty = rem / sx;
+      const int tx = rem - ty * sx;
+      const Tb3dGeom g = tb3d_geom<R>(tx, ty, sx, sy, P, Qy, uni(J.hx), uni(J.hy));
+      const int Zs0 = seg * seg_len;
+      const int Zs1 = (Zs0 + seg_len < Qz) ? Zs0 + seg_len : Qz;
+      tb3d_tile<Real, R, SHAPE, DEPTH>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, d, faces, xchg);
+    }
+    // every wave's stores are released before the count is published
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(q.done + job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+}  // namespace batch
+}  // namespace stencil_impl
+
+namespace stencil_impl {
+namespace batch {
+
+template <typename Real, int R, int SHAPE>
+hipError_t launch2d(const Batch2DParams<Real>* p, int grid, size_t lds, hipStream_t s) {
+  constexpr int D = max_depth_c(R, SHAPE);
+  if constexpr (D == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    const void* fn = (const void*)&tb2d_batch_kernel<Real, R, SHAPE, D>;
+    void* args[] = {(void*)p};
+    return hipLaunchKernel(fn, dim3(grid), dim3(256), args, lds, s);
+  }
+}
+
+template <typename Real, int R, int SHAPE>
+hipError_t launch3d(const Batch3DParams<Real>* p, int grid, hipStream_t s) {
+  constexpr int D = tb3d::max_depth_c(sizeof(Real) == 8 ? kF64 : kF32, R, SHAPE);
+  if constexpr (D == 0) {
+    return hipErrorInvalidValue;
+  } else {
+    const void* fn = (const void*)&tb3d_batch_kernel<Real, R, SHAPE, D>;
+    const size_t lds = tb3d::Lds<Real, R>::kBytes;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)p};
+    return hipLaunchKernel(fn, dim3(grid), dim3(tb3d::kThreads), args, lds, s);
+  }
+}
+
+template <typename Real, int R>
+hipError_t launch2d_shape(int shape, const Batch2DParams<Real>* p, int grid, size_t lds,
+                          hipStream_t s) {
+  switch (shape) {
+    case kStar: return launch2d<Real, R, kStar>(p, grid, lds, s);
+    case kBox: return launch2d<Real, R, kBox>(p, grid, lds, s);
+    case kGeneral: return launch2d<Real, R, kGeneral>(p, grid, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename Real, int R>
+hipError_t launch3d_shape(int shape, const Batch3DParams<Real>* p, int grid, hipStream_t s) {
+  switch (shape) {
+    case kStar: return launch3d<Real, R, kStar>(p, grid, s);
+    case kBox: return launch3d<Real, R, kBox>(p, grid, s);
+    case kGeneral: return launch3d<Real, R, kGeneral>(p, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace batch
+}  // namespace stencil_impl

@@ -16,12 +16,11 @@
 #include <vector>
 
 #include "launch.hpp"
+#include "plan.hpp"
 
 using namespace stencil_impl;
 
-namespace {
-
-constexpr int64_t kLdsBudget = 64 * 1024;
+namespace stencil_impl {
 
 thread_local std::string g_last_error;
 
@@ -39,11 +38,6 @@ stencil_status hip_fail(hipError_t e, const char* what) {
   return fail(STENCIL_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-struct DeviceInfo {
-  int cus = 0;
-  bool ok = false;
-};
-
 DeviceInfo device_info() {
   static std::mutex mu;
   static std::vector<DeviceInfo> cache;
@@ -60,38 +54,11 @@ DeviceInfo device_info() {
   return cache[dev];
 }
 
-}  // namespace
-
-struct stencil_plan_s {
-  int ndim = 0;
-  int r = 0;
-  int64_t n[3] = {1, 1, 1};    // interior extents, slowest first (3 entries used for 3D)
-  int64_t ext[3] = {1, 1, 1};  // padded extents padded to 3 axes (leading 1s for 2D)
-  int rad[3] = {0, 0, 0};      // halo width per padded axis
-  stencil_dtype dtype = STENCIL_F64;
-  int64_t T = 0;
-  std::vector<double> coeffs;  // dense box
-  int pattern = STENCIL_GENERAL;
-  int points = 0;
-  int scheme = STENCIL_SCHEME_NAIVE;
-  int depth = 1;
-  std::vector<int> pass_depth;  // depth of each pass
-  // 2D blocked geometry
-  int strips = 0, segs = 0, seg_len = 0, tiles = 0, hq_rows = 0, hl = 0;
-  // 3D blocked geometry
-  int sx = 0, sy = 0, hx = 0, hy = 0;
-  int grid = 0, block = 0;
-  int64_t cells = 0;
-  int64_t padded_elems = 0;
-  size_t elem = 8;
-  size_t workspace = 0;
-  // plain kernel taps (offset, weight), dense-box order
-  std::vector<int64_t> tap_off;
-  std::vector<double> tap_w;
-  bool plan_ok_3d(int) const { return r <= 2; }
-};
+}  // namespace stencil_impl
 
 namespace {
+
+constexpr int64_t kLdsBudget = 64 * 1024;
 
 bool classify(int ndim, int r, const double* c, int* pattern, int* points) {
   const int side = 2 * r + 1;
@@ -141,7 +108,8 @@ void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
   const int64_t mid_valid = (int64_t)(kWave - 2 * HL) * V;
   int64_t n_int = 0;
   if (nx > 2 * side_valid) n_int = (nx - 2 * side_valid + mid_valid - 1) / mid_valid;
-  p->strips = (int)(2 + n_int);
+  // an interior exactly one wave tile wide is one strip with halo on both sides
+  p->strips = nx == (int64_t)kWave * V ? 1 : (int)(2 + n_int);
   p->hl = HL;
   (void)W;
   int seg;
@@ -183,6 +151,7 @@ void plan_3d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
   auto strips = [&](int64_t n) {
     const int64_t side = (int64_t)(L - H) * B, mid = (int64_t)(L - 2 * H) * B;
     int64_t k = 0;
+    if (n == T) return 1;  // one tile exactly covers the interior
     if (n > 2 * side) k = (n - 2 * side + mid - 1) / mid;
     return (int)(2 + k);
   };

@@ -45,6 +45,73 @@ struct Tb3dParams {
   Real w[kMaxBox3D > 125 ? 125 : kMaxBox3D];  // dense (2r+1)^3 box, r <= 2
 };
 
+// ---- batched persistent execution ----------------------------------------
+// A batch runs many independent grids in persistent launches (one per kernel
+// variant). Work items are (job, pass, tile); they are listed as chunks (job,
+// pass) in an order where every pass of a job follows its previous pass, and
+// the item counter walks them. A tile of pass p of job j starts once all
+// tiles of pass p-1 of job j are done (done[j] >= p * tiles), which also
+// covers the reuse of the ping-pong buffers.
+struct BatchQueue {
+  const int32_t* chunk_job;
+  const int32_t* chunk_pass;
+  const int64_t* chunk_first;  // nchunks + 1 prefix sums of item counts
+  int32_t nchunks;
+  int64_t nitems;
+  unsigned long long* cursor;  // next item
+  unsigned int* done;          // per job: tiles finished, all passes
+  unsigned int* err;           // set when a bounded wait expires
+  int64_t timeout_ticks;       // s_memrealtime ticks (100 MHz)
+};
+
+template <typename Real>
+struct BatchJob2D {
+  const void* in;
+  void* out;
+  void* ws;
+  int64_t P, Q;
+  int32_t strips, segs, seg_len, tiles, hl, npass, depth, depth_last;
+  Real w[kMaxBox2D];
+};
+
+template <typename Real>
+struct BatchJob3D {
+  const void* in;
+  void* out;
+  void* ws;
+  int64_t P, Qy, Qz;
+  int32_t sx, sy, segs, seg_len, tiles, hx, hy, npass, depth, depth_last;
+  Real w[125];
+};
+
+template <typename Real>
+struct Batch2DParams {
+  const BatchJob2D<Real>* jobs;
+  BatchQueue q;
+  int32_t hq_rows;  // LDS halo rows per wave (maximum over the jobs)
+};
+
+template <typename Real>
+struct Batch3DParams {
+  const BatchJob3D<Real>* jobs;
+  BatchQueue q;
+};
+
+// Halo-frame copies for many grids in one launch.
+struct FrameCopyJob {
+  const void* src;
+  void* dst;
+  int64_t ext[3];
+  int32_t r[3];
+};
+
+hipError_t tb2d_batch_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
+                             size_t lds_bytes, hipStream_t stream);
+hipError_t tb3d_batch_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
+                             hipStream_t stream);
+hipError_t frame_copy_batch_launch(int dtype, const FrameCopyJob* jobs_dev, int njobs,
+                                   hipStream_t stream);
+
 // One step of the plain kernel, any ndim <= 3 (padded extents ext[0..2],
 // slowest first; unused leading extents are 1 with zero halo). The non-zero
 // taps (linear offset, weight) are passed by value in dense-box order.

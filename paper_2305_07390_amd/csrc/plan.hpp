@@ -1,0 +1,55 @@
+// Internal to the library: the plan object and helpers shared by capi.cpp
+// (single grids) and batch_host.cpp (batches).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/stencil.h"
+#include "launch.hpp"
+
+namespace stencil_impl {
+
+stencil_status fail(stencil_status st, const char* fmt, ...);
+stencil_status hip_fail(hipError_t e, const char* what);
+
+struct DeviceInfo {
+  int cus = 0;
+  bool ok = false;
+};
+DeviceInfo device_info();
+
+}  // namespace stencil_impl
+
+struct stencil_plan_s {
+  int ndim = 0;
+  int r = 0;
+  int64_t n[3] = {1, 1, 1};
+  // ^ interior extents, slowest first (padded to three axes)
+  int64_t ext[3] = {1, 1, 1};  // padded extents padded to 3 axes (leading 1s for 2D)
+  int rad[3] = {0, 0, 0};      // halo width per padded axis
+  stencil_dtype dtype = STENCIL_F64;
+  int64_t T = 0;
+  std::vector<double> coeffs;  // dense box
+  int pattern = STENCIL_GENERAL;
+  int points = 0;
+  int scheme = STENCIL_SCHEME_NAIVE;
+  int depth = 1;
+  std::vector<int> pass_depth;  // depth of each pass
+  // 2D blocked geometry
+  int strips = 0, segs = 0, seg_len = 0, tiles = 0, hq_rows = 0, hl = 0;
+  // 3D blocked geometry
+  int sx = 0, sy = 0, hx = 0, hy = 0;
+  int grid = 0, block = 0;
+  int64_t cells = 0;
+  int64_t padded_elems = 0;
+  size_t elem = 8;
+  size_t workspace = 0;
+  // plain kernel taps (offset, weight), dense-box order
+  std::vector<int64_t> tap_off;
+  std::vector<double> tap_w;
+  bool plan_ok_3d(int) const { return r <= 2; }
+};
+

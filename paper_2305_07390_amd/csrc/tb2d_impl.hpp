@@ -59,7 +59,7 @@ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 constexpr int lcm_c(int a, int b) { return a / gcd_c(a, b) * b; }
 constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
 
-enum Edge { kInterior = 0, kLeftEdge = 1, kRightEdge = 2 };
+enum Edge { kInterior = 0, kLeftEdge = 1, kRightEdge = 2, kBothEdges = 3 };
 
 template <typename Real>
 struct ColsPerLane {
@@ -144,6 +144,7 @@ struct Tb2dTile {
   __amdgpu_buffer_rsrc_t rs, rd;
   uint32_t col_off, st_off, row_bytes;
   int ys, Y0, Y1, Q, n_iter;
+  int d;  // levels of this pass (<= the compiled depth)
   int lo[17];
 };
 
@@ -170,6 +171,7 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
 
 #pragma unroll
   for (int s = 1; s <= DEPTH; ++s) {
+    if (s > t.d) break;
     const int u = y - (s - 1) * R;  // row of level s-1 arriving now
     const bool ok = !GENERAL || ((u >= t.lo[s - 1]) && (u < Q));
     // halo values of row u (two copies, so each DPP gets its own register)
@@ -220,36 +222,39 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) x[v] = out[v];
+    if (s == t.d) {
+      // the last level completed row y - d*r
+      const int o = y - s * R;
+      if (!GENERAL || (o >= t.Y0 && o < t.Y1))
+        store_vec<Real, V>(t.rd, t.st_off + (uint32_t)(o - t.Y0) * t.row_bytes, 0, x);
+    }
   }
-  // level DEPTH completed row y - DEPTH*r
-  const int o = y - DEPTH * R;
-  if (!GENERAL || (o >= t.Y0 && o < t.Y1))
-    store_vec<Real, V>(t.rd, t.st_off + (uint32_t)(o - t.Y0) * t.row_bytes, 0, x);
 }
 
+// One wave tile of one pass: d (<= DEPTH) levels from src to dst.
 template <typename Real, int R, int SHAPE, int DEPTH, int V>
-__device__ __forceinline__ void tb2d_tile(const Tb2dParams<Real>& a, Real* hq, const int lane,
-                                          const int edge, const int X0, const int la, const int lb,
-                                          const int Y0, const int Y1) {
+__device__ __forceinline__ void tb2d_tile(const Real* __restrict__ w, const void* src, void* dst,
+                                          const void* orig, const int P, const int Q, Real* hq,
+                                          const int lane, const int edge, const int X0,
+                                          const int la, const int lb, const int Y0, const int Y1,
+                                          const int d) {
   constexpr int R2 = 2 * R;
   constexpr int Z0 = Ring0<R>::value;
   constexpr int UNROLL = lcm_c(R2, Z0);
   constexpr int S = sizeof(Real);
-  const int P = (int)a.P;
-  const int Q = (int)a.Q;
-  const Real* __restrict__ w = a.w;
 
   Tb2dTile t;
+  t.d = d;
   t.Q = Q;
   t.Y0 = Y0;
   t.Y1 = Y1;
-  t.ys = Y0 - DEPTH * R > 0 ? Y0 - DEPTH * R : 0;
-  const int ye = Y1 - 1 + DEPTH * R;
+  t.ys = Y0 - d * R > 0 ? Y0 - d * R : 0;
+  const int ye = Y1 - 1 + d * R;
   t.n_iter = ye - t.ys + 1;
   int64_t src_range = (int64_t)(Q - t.ys) * P * S;
   if (src_range > 0xffffffffll) src_range = 0xffffffffll;
-  t.rs = make_rsrc((const char*)a.src + (int64_t)t.ys * P * S, (uint32_t)src_range);
-  t.rd = make_rsrc((char*)a.dst + (int64_t)Y0 * P * S, (uint32_t)((int64_t)(Y1 - Y0) * P * S));
+  t.rs = make_rsrc((const char*)src + (int64_t)t.ys * P * S, (uint32_t)src_range);
+  t.rd = make_rsrc((char*)dst + (int64_t)Y0 * P * S, (uint32_t)((int64_t)(Y1 - Y0) * P * S));
   t.row_bytes = (uint32_t)(P * S);
   t.col_off = (uint32_t)((X0 + lane * V) * S);
   // lanes outside the store range get an offset past the descriptor: the
@@ -258,7 +263,7 @@ __device__ __forceinline__ void tb2d_tile(const Tb2dParams<Real>& a, Real* hq, c
   t.lo[0] = t.ys;
 #pragma unroll
   for (int s = 1; s <= DEPTH; ++s) {
-    const int b = Y0 - (DEPTH - s) * R;
+    const int b = Y0 - (d - s) * R;
     t.lo[s] = b > 0 ? b : 0;
   }
 
@@ -266,15 +271,16 @@ __device__ __forceinline__ void tb2d_tile(const Tb2dParams<Real>& a, Real* hq, c
   // (left strip: columns 0..r-1, right strip: columns P-r..P-1), two copies
   // per row.
   if (edge != kInterior) {
-    const int c0 = edge == kLeftEdge ? 0 : P - R;
     const int rows = (ye < Q - 1 ? ye : Q - 1) - t.ys + 1;
     const __amdgpu_buffer_rsrc_t rin =
-        make_rsrc((const char*)a.orig + (int64_t)t.ys * P * S, (uint32_t)src_range);
+        make_rsrc((const char*)orig + (int64_t)t.ys * P * S, (uint32_t)src_range);
     for (int k = lane; k < rows * R; k += kWave) {
       const int row = k / R, j = k - row * R;
-      const Real h = load_one<Real>(rin, (uint32_t)(row * P + c0 + j) * S, 0);
-      hq[row * 2 * R + j] = h;
-      hq[row * 2 * R + R + j] = h;
+      // left copy feeds lane 0, right copy feeds lane 63
+      const Real hl = load_one<Real>(rin, (uint32_t)(row * P + j) * S, 0);
+      const Real hr = load_one<Real>(rin, (uint32_t)(row * P + P - R + j) * S, 0);
+      hq[row * 2 * R + j] = edge == kRightEdge ? hr : hl;
+      hq[row * 2 * R + R + j] = edge == kLeftEdge ? hl : hr;
     }
   }
 
@@ -296,9 +302,10 @@ __device__ __forceinline__ void tb2d_tile(const Tb2dParams<Real>& a, Real* hq, c
 
   // Steady rows: every level holds valid rows, no halo row is touched and the
   // completed row is stored.
-  int y_a = t.lo[DEPTH - 1] + (DEPTH - 1) * R;
-  if (y_a < (DEPTH + 1) * R) y_a = (DEPTH + 1) * R;
-  if (y_a < Y0 + DEPTH * R) y_a = Y0 + DEPTH * R;
+  const int lo_dm1 = Y0 - R > 0 ? Y0 - R : 0;  // lowest valid row of level d-1
+  int y_a = lo_dm1 + (d - 1) * R;
+  if (y_a < (d + 1) * R) y_a = (d + 1) * R;
+  if (y_a < Y0 + d * R) y_a = Y0 + d * R;
   int y_b = Q - 2 * R;
   if (y_b > ye + 1) y_b = ye + 1;
   int i_a = y_a - t.ys;
@@ -345,7 +352,10 @@ __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
     const int Y0 = seg * a.seg_len;
     const int Y1 = (Y0 + a.seg_len < Q) ? Y0 + a.seg_len : Q;
     int edge, X0, la, lb;
-    if (strip == 0) {
+    if (ns == 1) {
+      // one strip exactly as wide as the interior: both sides are halo
+      edge = kBothEdges; X0 = R; la = 0; lb = kWave;
+    } else if (strip == 0) {
       edge = kLeftEdge; X0 = R; la = 0; lb = kWave - HL;
     } else if (strip == ns - 1) {
       edge = kRightEdge; X0 = P - R - W; la = HL; lb = kWave;
@@ -354,7 +364,8 @@ __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
       X0 = R + (kWave - HL) * V + (strip - 1) * (kWave - 2 * HL) * V - HL * V;
       la = HL; lb = kWave - HL;
     }
-    tb2d_tile<Real, R, SHAPE, DEPTH, V>(a, hq, lane, edge, X0, la, lb, Y0, Y1);
+    tb2d_tile<Real, R, SHAPE, DEPTH, V>(a.w, a.src, a.dst, a.orig, P, Q, hq, lane, edge, X0, la,
+                                        lb, Y0, Y1, DEPTH);
   }
 }
 

@@ -94,7 +94,9 @@ struct FaceLayout {
   static constexpr int kPerPlane = 2 * R * TY + 2 * R * (TX + 2 * R);
 };
 
-// Exchange buffer layout: per lane, its top R rows then bottom R rows, each
+// Exchange buffer layout, element-major so that consecutive lanes touch
+// consecutive words (no bank conflicts): element e of lane l at e * 256 + l,
+// elements = top R rows then bottom R rows of the lane's block, each
 // (BX + 2R) wide (x-extended).
 template <int R>
 struct XchgLayout {
@@ -125,6 +127,7 @@ struct Tile {
   uint32_t st_off;      // same, or past the descriptor for lanes outside the valid range
   uint32_t plane_bytes, row_bytes;
   int zs, Z0, Z1, Qz, n_iter;
+  int d;  // levels of this pass (<= the compiled depth)
   int lo[13];
   // face cells this lane loads (plane-relative byte offset, face queue index)
   uint32_t f_off[3];
@@ -197,6 +200,7 @@ __device__ __forceinline__ void plane_step(State<Real, R, DEPTH>& st, const Tile
 
 #pragma unroll
   for (int s = 1; s <= DEPTH; ++s) {
+    if (s > t.d) break;
     const int u = z - (s - 1) * R;  // plane of level s-1 arriving now
     const bool ok = !GENERAL || ((u >= t.lo[s - 1]) && (u < Qz));
     const Real* fp = faces + ((u < 0 ? 0 : u) & (kRing - 1)) * FL::kPerPlane;
@@ -220,32 +224,34 @@ __device__ __forceinline__ void plane_step(State<Real, R, DEPTH>& st, const Tile
     // buffers they alternate with the running level count (even per unrolled
     // block), so one barrier per level separates every write from the last
     // read of the same buffer.
-    Real* xb = xchg + (XL::kBufs == 2 ? ((ph * DEPTH + s) & 1) * XL::kPerBuf : 0);
+    Real* xb = xchg + (XL::kBufs == 2 ? ((ph * t.d + s) & 1) * XL::kPerBuf : 0);
     {
-      Real* mine = xb + lane_id_t * XL::kPerLane;
 #pragma unroll
       for (int c = 0; c < R; ++c)
 #pragma unroll
         for (int q = 0; q < XL::kRowW; ++q) {
-          mine[c * XL::kRowW + q] = ext[R + c][q];                 // top rows
-          mine[(R + c) * XL::kRowW + q] = ext[R + BY - R + c][q];  // bottom rows
+          xb[(c * XL::kRowW + q) * kThreads + lane_id_t] = ext[R + c][q];            // top rows
+          xb[((R + c) * XL::kRowW + q) * kThreads + lane_id_t] = ext[BY + c][q];     // bottom rows
         }
     }
     __syncthreads();
     {
-      // rows above: bottom rows of the lane above, or the top face
-      const Real* above = ly > 0 ? xb + (lane_id_t - LX) * XL::kPerLane + R * XL::kRowW
-                                 : fp + FL::kTop + lx * BX;  // (c, x) -> c*(TX+2R) + x
-      const int astride = ly > 0 ? XL::kRowW : TX + 2 * R;
-      const Real* below = ly < LY - 1 ? xb + (lane_id_t + LX) * XL::kPerLane
-                                      : fp + FL::kBottom + lx * BX;
-      const int bstride = ly < LY - 1 ? XL::kRowW : TX + 2 * R;
+      // rows above: bottom rows of the lane above, or the top face; rows below:
+      // top rows of the lane below, or the bottom face
+      const bool in_a = ly > 0, in_b = ly < LY - 1;
+      const Real* above = in_a ? xb + R * XL::kRowW * kThreads + (lane_id_t - LX)
+                               : fp + FL::kTop + lx * BX;
+      const int a_c = in_a ? XL::kRowW * kThreads : TX + 2 * R;
+      const int a_q = in_a ? kThreads : 1;
+      const Real* below = in_b ? xb + (lane_id_t + LX) : fp + FL::kBottom + lx * BX;
+      const int b_c = in_b ? XL::kRowW * kThreads : TX + 2 * R;
+      const int b_q = in_b ? kThreads : 1;
 #pragma unroll
       for (int c = 0; c < R; ++c)
 #pragma unroll
         for (int q = 0; q < XL::kRowW; ++q) {
-          ext[c][q] = above[c * astride + q];
-          ext[R + BY + c][q] = below[c * bstride + q];
+          ext[c][q] = above[c * a_c + q * a_q];
+          ext[R + BY + c][q] = below[c * b_c + q * b_q];
         }
     }
     if (XL::kBufs == 1) __syncthreads();
@@ -291,162 +297,188 @@ __device__ __forceinline__ void plane_step(State<Real, R, DEPTH>& st, const Tile
     for (int j = 0; j < BY; ++j)
 #pragma unroll
       for (int q = 0; q < BX; ++q) x[j][q] = out[j][q];
-  }
-  const int o = z - DEPTH * R;
-  if (!GENERAL || (o >= t.Z0 && o < t.Z1)) {
-    const uint32_t pb = (uint32_t)(o - t.Z0) * t.plane_bytes;
+    if (s == t.d) {
+      // the last level completed plane z - d*r
+      const int o = z - s * R;
+      if (!GENERAL || (o >= t.Z0 && o < t.Z1)) {
+        const uint32_t pb = (uint32_t)(o - t.Z0) * t.plane_bytes;
 #pragma unroll
-    for (int j = 0; j < BY; ++j) store_vec<Real, BX>(t.rd, t.st_off + pb + (uint32_t)j * t.row_bytes, 0, x[j]);
+        for (int j = 0; j < BY; ++j)
+          store_vec<Real, BX>(t.rd, t.st_off + pb + (uint32_t)j * t.row_bytes, 0, x[j]);
+      }
+    }
+  }
+}
+
+// Geometry of tile (tx, ty) of an sx x sy tiling with hx / hy redundant lanes.
+struct Tb3dGeom {
+  int X0, lxa, lxb, Y0, lya, lyb;
+};
+template <int R>
+__device__ __forceinline__ Tb3dGeom tb3d_geom(int tx, int ty, int sx, int sy, int P, int Qy, int HX,
+                                              int HY) {
+  Tb3dGeom g;
+  // a single tile exactly as wide (tall) as the interior has halo on both sides
+  if (sx == 1) { g.X0 = R; g.lxa = 0; g.lxb = LX; }
+  else if (tx == 0) { g.X0 = R; g.lxa = 0; g.lxb = LX - HX; }
+  else if (tx == sx - 1) { g.X0 = P - R - TX; g.lxa = HX; g.lxb = LX; }
+  else { g.X0 = R + (LX - HX) * BX + (tx - 1) * (LX - 2 * HX) * BX - HX * BX; g.lxa = HX; g.lxb = LX - HX; }
+  if (sy == 1) { g.Y0 = R; g.lya = 0; g.lyb = LY; }
+  else if (ty == 0) { g.Y0 = R; g.lya = 0; g.lyb = LY - HY; }
+  else if (ty == sy - 1) { g.Y0 = Qy - R - TY; g.lya = HY; g.lyb = LY; }
+  else { g.Y0 = R + (LY - HY) * BY + (ty - 1) * (LY - 2 * HY) * BY - HY * BY; g.lya = HY; g.lyb = LY - HY; }
+  return g;
+}
+
+// One workgroup tile of one pass: d (<= DEPTH) levels from src to dst over the
+// planes [Zs0, Zs1) of the xy tile g. Every thread of the workgroup calls it.
+template <typename Real, int R, int SHAPE, int DEPTH>
+__device__ __forceinline__ void tb3d_tile(const Real* __restrict__ w, const void* src, void* dst,
+                                          const int P, const int Qy, const int Qz,
+                                          const Tb3dGeom g, const int Zs0, const int Zs1,
+                                          const int d, Real* faces, Real* xchg) {
+  using FL = FaceLayout<R>;
+  constexpr int Z0 = State<Real, R, DEPTH>::Z0;
+  constexpr int UNROLL = (2 * R) % Z0 == 0 ? 2 * R : 2 * R * Z0;
+  constexpr int S = sizeof(Real);
+  const int tid = threadIdx.x;
+  const int lx = tid % LX;
+  const int ly = tid / LX;
+  const int X0 = g.X0, Y0 = g.Y0;
+
+  Tile t;
+  t.d = d;
+  t.Qz = Qz;
+  t.Z0 = Zs0;
+  t.Z1 = Zs1;
+  t.zs = Zs0 - d * R > 0 ? Zs0 - d * R : 0;
+  const int ze = Zs1 - 1 + d * R;
+  t.n_iter = ze - t.zs + 1;
+  t.row_bytes = (uint32_t)(P * S);
+  t.plane_bytes = (uint32_t)((int64_t)P * Qy * S);
+  int64_t range = (int64_t)(Qz - t.zs) * P * Qy * S;
+  if (range > 0xffffffffll) range = 0xffffffffll;
+  t.rs = make_rsrc((const char*)src + (int64_t)t.zs * P * Qy * S, (uint32_t)range);
+  t.rd = make_rsrc((char*)dst + (int64_t)Zs0 * P * Qy * S,
+                   (uint32_t)((int64_t)(Zs1 - Zs0) * P * Qy * S));
+  t.blk_off = (uint32_t)(((Y0 + ly * BY) * P + X0 + lx * BX) * S);
+  const bool valid = lx >= g.lxa && lx < g.lxb && ly >= g.lya && ly < g.lyb;
+  t.st_off = valid ? t.blk_off : 0x80000000u;
+  t.lo[0] = t.zs;
+#pragma unroll
+  for (int s = 1; s <= DEPTH; ++s) {
+    const int b = Zs0 - (d - s) * R;
+    t.lo[s] = b > 0 ? b : 0;
+  }
+  // face cells handled by this thread: thread k takes face entries k, k+256, ...
+  t.n_f = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int e = tid + k * kThreads;
+    t.f_off[k] = 0;
+    t.f_idx[k] = 0;
+    if (e < FL::kPerPlane) {
+      int fx, fy;
+      if (e < FL::kRight) { const int c = e / TY, j = e % TY; fx = X0 - R + c; fy = Y0 + j; }
+      else if (e < FL::kTop) { const int f = e - FL::kRight; const int c = f / TY, j = f % TY; fx = X0 + TX + c; fy = Y0 + j; }
+      else if (e < FL::kBottom) { const int f = e - FL::kTop; const int c = f / (TX + 2 * R), q = f % (TX + 2 * R); fy = Y0 - R + c; fx = X0 - R + q; }
+      else { const int f = e - FL::kBottom; const int c = f / (TX + 2 * R), q = f % (TX + 2 * R); fy = Y0 + TY + c; fx = X0 - R + q; }
+      // cells outside the padded plane are never needed by a valid cell: clamp
+      fx = fx < 0 ? 0 : (fx >= P ? P - 1 : fx);
+      fy = fy < 0 ? 0 : (fy >= Qy ? Qy - 1 : fy);
+      t.f_off[k] = (uint32_t)((fy * P + fx) * S);
+      t.f_idx[k] = e;
+      t.n_f = k + 1;
+    }
+  }
+
+  State<Real, R, DEPTH> st;
+#pragma unroll
+  for (int zz = 0; zz < Z0; ++zz) {
+#pragma unroll
+    for (int j = 0; j < BY; ++j)
+#pragma unroll
+      for (int q = 0; q < BX; ++q) st.L0[zz][j][q] = Real(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) st.F[zz][k] = Real(0);
+  }
+#pragma unroll
+  for (int s = 0; s < DEPTH; ++s)
+#pragma unroll
+    for (int sl = 0; sl < 2 * R; ++sl)
+#pragma unroll
+      for (int j = 0; j < BY; ++j)
+#pragma unroll
+        for (int q = 0; q < BX; ++q) st.A[s][sl][j][q] = Real(0);
+
+  // prologue: planes 0 and 1 (blocks and faces), face queue slot of plane 0
+  __syncthreads();  // the previous tile is done with the LDS queues
+#pragma unroll
+  for (int p = 0; p < Z0; ++p) {
+    if (p < t.n_iter) {
+      const uint32_t pb = (uint32_t)p * t.plane_bytes;
+#pragma unroll
+      for (int j = 0; j < BY; ++j)
+        load_vec<Real, BX>(t.rs, t.blk_off + pb + (uint32_t)j * t.row_bytes, 0, st.L0[p][j]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (k < t.n_f) st.F[p][k] = load_one<Real>(t.rs, t.f_off[k] + pb, 0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    if (k < t.n_f) faces[(t.zs & (kRing - 1)) * FL::kPerPlane + t.f_idx[k]] = st.F[0][k];
+  __syncthreads();
+
+  // steady planes: every level valid, no halo plane touched, output stored
+  const int lo_dm1 = Zs0 - R > 0 ? Zs0 - R : 0;  // lowest valid plane of level d-1
+  int z_a = lo_dm1 + (d - 1) * R;
+  if (z_a < (d + 1) * R) z_a = (d + 1) * R;
+  if (z_a < Zs0 + d * R) z_a = Zs0 + d * R;
+  int z_b = Qz - 2 * R;
+  if (z_b > ze + 1) z_b = ze + 1;
+  int i_a = z_a - t.zs;
+  i_a = (i_a + UNROLL - 1) / UNROLL * UNROLL;
+  int i_b = (z_b - t.zs) / UNROLL * UNROLL;
+  if (i_a > t.n_iter) i_a = (t.n_iter / UNROLL) * UNROLL;
+  if (i_b < i_a) i_b = i_a;
+
+  int base = 0;
+  for (; base < i_a; base += UNROLL) {
+#pragma unroll
+    for (int ph = 0; ph < UNROLL; ++ph)
+      if (base + ph < t.n_iter)
+        plane_step<Real, R, SHAPE, DEPTH, true>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
+  }
+  for (; base < i_b; base += UNROLL) {
+#pragma unroll
+    for (int ph = 0; ph < UNROLL; ++ph)
+      plane_step<Real, R, SHAPE, DEPTH, false>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
+  }
+  for (; base < t.n_iter; base += UNROLL) {
+#pragma unroll
+    for (int ph = 0; ph < UNROLL; ++ph)
+      if (base + ph < t.n_iter)
+        plane_step<Real, R, SHAPE, DEPTH, true>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
   }
 }
 
 template <typename Real, int R, int SHAPE, int DEPTH>
 __global__ __launch_bounds__(kThreads) void tb3d_kernel(const Tb3dParams<Real> a) {
   using FL = FaceLayout<R>;
-  using XL = XchgLayout<R>;
-  constexpr int Z0 = State<Real, R, DEPTH>::Z0;
-  constexpr int UNROLL = (2 * R) % Z0 == 0 ? 2 * R : 2 * R * Z0;
-  constexpr int S = sizeof(Real);
   extern __shared__ char lds_raw[];
   Real* faces = (Real*)lds_raw;
   Real* xchg = faces + kRing * FL::kPerPlane;
-
-  const int tid = threadIdx.x;
-  const int lx = tid % LX;
-  const int ly = tid / LX;
   const int P = (int)a.P, Qy = (int)a.Qy, Qz = (int)a.Qz;
-  const int HX = a.hx, HY = a.hy;  // redundant lanes per open side
-  const Real* __restrict__ w = a.w;
-
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const int seg = tile / (a.sx * a.sy);
     const int rem = tile - seg * a.sx * a.sy;
     const int ty = rem / a.sx;
     const int tx = rem - ty * a.sx;
-    // strip origins (first interior cell of the grid is R) and valid lane ranges
-    int X0, lxa, lxb, Y0, lya, lyb;
-    if (tx == 0) { X0 = R; lxa = 0; lxb = LX - HX; }
-    else if (tx == a.sx - 1) { X0 = P - R - TX; lxa = HX; lxb = LX; }
-    else { X0 = R + (LX - HX) * BX + (tx - 1) * (LX - 2 * HX) * BX - HX * BX; lxa = HX; lxb = LX - HX; }
-    if (ty == 0) { Y0 = R; lya = 0; lyb = LY - HY; }
-    else if (ty == a.sy - 1) { Y0 = Qy - R - TY; lya = HY; lyb = LY; }
-    else { Y0 = R + (LY - HY) * BY + (ty - 1) * (LY - 2 * HY) * BY - HY * BY; lya = HY; lyb = LY - HY; }
+    const Tb3dGeom g = tb3d_geom<R>(tx, ty, a.sx, a.sy, P, Qy, a.hx, a.hy);
     const int Zs0 = seg * a.seg_len;
     const int Zs1 = (Zs0 + a.seg_len < Qz) ? Zs0 + a.seg_len : Qz;
-
-    Tile t;
-    t.Qz = Qz;
-    t.Z0 = Zs0;
-    t.Z1 = Zs1;
-    t.zs = Zs0 - DEPTH * R > 0 ? Zs0 - DEPTH * R : 0;
-    const int ze = Zs1 - 1 + DEPTH * R;
-    t.n_iter = ze - t.zs + 1;
-    t.row_bytes = (uint32_t)(P * S);
-    t.plane_bytes = (uint32_t)((int64_t)P * Qy * S);
-    int64_t range = (int64_t)(Qz - t.zs) * P * Qy * S;
-    if (range > 0xffffffffll) range = 0xffffffffll;
-    t.rs = make_rsrc((const char*)a.src + (int64_t)t.zs * P * Qy * S, (uint32_t)range);
-    t.rd = make_rsrc((char*)a.dst + (int64_t)Zs0 * P * Qy * S,
-                     (uint32_t)((int64_t)(Zs1 - Zs0) * P * Qy * S));
-    t.blk_off = (uint32_t)(((Y0 + ly * BY) * P + X0 + lx * BX) * S);
-    const bool valid = lx >= lxa && lx < lxb && ly >= lya && ly < lyb;
-    t.st_off = valid ? t.blk_off : 0x80000000u;
-    t.lo[0] = t.zs;
-#pragma unroll
-    for (int s = 1; s <= DEPTH; ++s) {
-      const int b = Zs0 - (DEPTH - s) * R;
-      t.lo[s] = b > 0 ? b : 0;
-    }
-    // face cells handled by this thread: thread k takes face entries k, k+256, ...
-    t.n_f = 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int e = tid + k * kThreads;
-      t.f_off[k] = 0;
-      t.f_idx[k] = 0;
-      if (e < FL::kPerPlane) {
-        int fx, fy;
-        if (e < FL::kRight) { const int c = e / TY, j = e % TY; fx = X0 - R + c; fy = Y0 + j; }
-        else if (e < FL::kTop) { const int f = e - FL::kRight; const int c = f / TY, j = f % TY; fx = X0 + TX + c; fy = Y0 + j; }
-        else if (e < FL::kBottom) { const int f = e - FL::kTop; const int c = f / (TX + 2 * R), q = f % (TX + 2 * R); fy = Y0 - R + c; fx = X0 - R + q; }
-        else { const int f = e - FL::kBottom; const int c = f / (TX + 2 * R), q = f % (TX + 2 * R); fy = Y0 + TY + c; fx = X0 - R + q; }
-        // cells outside the padded plane are never needed by a valid cell: clamp
-        fx = fx < 0 ? 0 : (fx >= P ? P - 1 : fx);
-        fy = fy < 0 ? 0 : (fy >= Qy ? Qy - 1 : fy);
-        t.f_off[k] = (uint32_t)((fy * P + fx) * S);
-        t.f_idx[k] = e;
-        t.n_f = k + 1;
-      }
-    }
-
-    State<Real, R, DEPTH> st;
-#pragma unroll
-    for (int zz = 0; zz < Z0; ++zz) {
-#pragma unroll
-      for (int j = 0; j < BY; ++j)
-#pragma unroll
-        for (int q = 0; q < BX; ++q) st.L0[zz][j][q] = Real(0);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) st.F[zz][k] = Real(0);
-    }
-#pragma unroll
-    for (int s = 0; s < DEPTH; ++s)
-#pragma unroll
-      for (int sl = 0; sl < 2 * R; ++sl)
-#pragma unroll
-        for (int j = 0; j < BY; ++j)
-#pragma unroll
-          for (int q = 0; q < BX; ++q) st.A[s][sl][j][q] = Real(0);
-
-    // prologue: planes 0 and 1 (blocks and faces), face queue slot of plane 0
-    __syncthreads();  // the previous tile is done with the LDS queue
-#pragma unroll
-    for (int p = 0; p < Z0; ++p) {
-      if (p < t.n_iter) {
-        const uint32_t pb = (uint32_t)p * t.plane_bytes;
-#pragma unroll
-        for (int j = 0; j < BY; ++j)
-          load_vec<Real, BX>(t.rs, t.blk_off + pb + (uint32_t)j * t.row_bytes, 0, st.L0[p][j]);
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          if (k < t.n_f) st.F[p][k] = load_one<Real>(t.rs, t.f_off[k] + pb, 0);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-      if (k < t.n_f) faces[(t.zs & (kRing - 1)) * FL::kPerPlane + t.f_idx[k]] = st.F[0][k];
-    __syncthreads();
-
-    // steady planes: every level valid, no halo plane touched, output stored
-    int z_a = t.lo[DEPTH - 1] + (DEPTH - 1) * R;
-    if (z_a < (DEPTH + 1) * R) z_a = (DEPTH + 1) * R;
-    if (z_a < Zs0 + DEPTH * R) z_a = Zs0 + DEPTH * R;
-    int z_b = Qz - 2 * R;
-    if (z_b > ze + 1) z_b = ze + 1;
-    int i_a = z_a - t.zs;
-    i_a = (i_a + UNROLL - 1) / UNROLL * UNROLL;
-    int i_b = (z_b - t.zs) / UNROLL * UNROLL;
-    if (i_a > t.n_iter) i_a = (t.n_iter / UNROLL) * UNROLL;
-    if (i_b < i_a) i_b = i_a;
-
-    int base = 0;
-    for (; base < i_a; base += UNROLL) {
-#pragma unroll
-      for (int ph = 0; ph < UNROLL; ++ph)
-        if (base + ph < t.n_iter)
-          plane_step<Real, R, SHAPE, DEPTH, true>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
-    }
-    for (; base < i_b; base += UNROLL) {
-#pragma unroll
-      for (int ph = 0; ph < UNROLL; ++ph)
-        plane_step<Real, R, SHAPE, DEPTH, false>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
-    }
-    for (; base < t.n_iter; base += UNROLL) {
-#pragma unroll
-      for (int ph = 0; ph < UNROLL; ++ph)
-        if (base + ph < t.n_iter)
-          plane_step<Real, R, SHAPE, DEPTH, true>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
-    }
+    tb3d_tile<Real, R, SHAPE, DEPTH>(a.w, a.src, a.dst, P, Qy, Qz, g, Zs0, Zs1, DEPTH, faces, xchg);
   }
 }
 

@@ -75,6 +75,13 @@ class stencil_plan_info(ctypes.Structure):
         return d
 
 
+class stencil_job(ctypes.Structure):
+    _fields_ = [("coeffs", ctypes.POINTER(ctypes.c_double)), ("radius", ctypes.c_int32),
+                ("shape", stencil_shape), ("dtype", ctypes.c_int), ("T", ctypes.c_int64),
+                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("tag", ctypes.c_uint64),
+                ("depth", ctypes.c_int32)]
+
+
 class stencil_model_params(ctypes.Structure):
     _fields_ = [("B_gm", ctypes.c_double), ("B_sm", ctypes.c_double), ("thr_cmp", ctypes.c_double),
                 ("cell_bytes", ctypes.c_double), ("a_gm", ctypes.c_double),
@@ -108,6 +115,9 @@ _SIGNATURES = {
     "stencil_plan_destroy": (ctypes.c_int, [_P]),
     "stencil_run": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape),
                                     ctypes.c_int, ctypes.c_int64, _P, _P, _P]),
+    "stencil_batch_submit": (ctypes.c_int, [ctypes.POINTER(stencil_job), ctypes.c_int32, _P,
+                                             ctypes.POINTER(ctypes.c_int)]),
+    "stencil_sync": (ctypes.c_int, [_P]),
     "stencil_model_eval": (ctypes.c_int, [ctypes.POINTER(stencil_model_params),
                                            ctypes.POINTER(stencil_model_result)]),
     "stencil_last_error": (ctypes.c_char_p, []),
@@ -202,6 +212,46 @@ def stencil_execute(plan, in_ptr: int, out_ptr: int, ws_ptr: int, stream: int = 
 
 def stencil_plan_destroy(plan):
     _check(load_library().stencil_plan_destroy(plan))
+
+
+def stencil_batch_submit(specs, stream: int = 0):
+    """Submit a batch. `specs` is a list of dicts with keys coeffs, radius,
+    interior, dtype, T, in_ptr, out_ptr and optional tag, depth. Returns the
+    per-job status list; raises StencilError if the call itself fails."""
+    lib = load_library()
+    n = len(specs)
+    arr = (stencil_job * n)()
+    keep = []
+    for i, sp in enumerate(specs):
+        c, cp = _coeff_ptr(sp["coeffs"])
+        keep.append(c)
+        arr[i].coeffs = cp
+        arr[i].radius = int(sp["radius"])
+        arr[i].shape = _shape(sp["interior"])
+        arr[i].dtype = _dtype_code(sp["dtype"])
+        arr[i].T = int(sp["T"])
+        arr[i].in_ = sp["in_ptr"]
+        arr[i].out = sp["out_ptr"]
+        arr[i].tag = int(sp.get("tag", i))
+        arr[i].depth = int(sp.get("depth", 0))
+    st = (ctypes.c_int * n)()
+    _check(lib.stencil_batch_submit(arr, n, stream or None, st))
+    return list(st)
+
+
+def stencil_sync(stream: int = 0):
+    _check(load_library().stencil_sync(stream or None))
+
+
+def run_batch(problems, xs, ys, stream=None, depth=0):
+    """Submit torch tensors (lists of inputs and outputs) as one batch on
+    `stream`; `problems` provide coefficients, radius and T."""
+    specs = []
+    for k, (prob, x, y) in enumerate(zip(problems, xs, ys)):
+        specs.append(dict(coeffs=prob.coeffs, radius=prob.spec.r, interior=prob.interior,
+                          dtype=x.dtype, T=prob.T, in_ptr=x.data_ptr(), out_ptr=y.data_ptr(),
+                          tag=getattr(prob, "tag", k), depth=depth))
+    return stencil_batch_submit(specs, _stream_handle(stream))
 
 
 def stencil_model_eval(**kw) -> dict:

@@ -151,7 +151,9 @@ def test_plan_choices():
 def _strip_columns(P, R, V, HL, ns, strip):
     """Mirror of the device strip layout: (loaded column range, stored column range)."""
     W = 64 * V
-    if strip == 0:
+    if ns == 1:
+        X0, la, lb = R, 0, 64
+    elif strip == 0:
         X0, la, lb = R, 0, 64 - HL
     elif strip == ns - 1:
         X0, la, lb = P - R - W, HL, 64
@@ -185,7 +187,27 @@ def test_strip_layout_covers_interior(dtype, r, kind):
             for sidx in range(ns):
                 (l0, l1), (s0, s1) = _strip_columns(P, r, V, HL, ns, sidx)
                 assert r <= l0 and l1 <= P - r, (nx, T, sidx, l0, l1)
-                if 0 < sidx < ns - 1:
+                if ns > 1 and 0 < sidx < ns - 1:
                     assert s0 - l0 >= i["depth"] * r and l1 - s1 >= i["depth"] * r
                 covered[s0:s1] = True
             assert covered[r:P - r].all(), (nx, T)
+
+
+def test_batch_rejects_shared_outputs_before_device_work():
+    _lib()
+    w = wl.uniform_5pt_coeffs()
+    fake = 1 << 40
+    nbytes = 302 * 302 * 8
+    specs = [dict(coeffs=w, radius=1, interior=(300, 300), dtype="float64", T=5,
+                  in_ptr=fake, out_ptr=fake + 4 * nbytes),
+             dict(coeffs=w, radius=1, interior=(300, 300), dtype="float64", T=5,
+                  in_ptr=fake + 8 * nbytes, out_ptr=fake + 4 * nbytes + 64)]
+    with pytest.raises(st.StencilError) as e:
+        st.stencil_batch_submit(specs, 0)
+    assert e.value.status == st.STENCIL_ERR_ALIAS
+    # a job whose own in and out overlap is reported per job; with no valid job left the call fails
+    specs = [dict(coeffs=w, radius=1, interior=(300, 300), dtype="float64", T=5,
+                  in_ptr=fake, out_ptr=fake + 100)]
+    with pytest.raises(st.StencilError) as e:
+        st.stencil_batch_submit(specs, 0)
+    assert e.value.status == st.STENCIL_ERR_INVALID

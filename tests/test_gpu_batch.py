@@ -1,0 +1,81 @@
+"""Batched persistent execution: every job of a mixed batch equals its own
+single-grid run and the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_07390_amd import stencil as st
+from paper_2305_07390_amd import workloads as wl
+from tests.gpu_util import gpu_sweep
+
+pytestmark = pytest.mark.gpu
+
+
+def _mixed_problems(dtype, seed=5):
+    rng = np.random.default_rng(seed)
+    probs = []
+    kinds = [(2, "star", 1), (2, "box", 1), (2, "star", 3), (2, "box", 2), (3, "star", 1),
+             (3, "box", 1), (3, "star", 2)]
+    for g in range(14):
+        ndim, kind, r = kinds[g % len(kinds)]
+        spec = wl.StencilSpec(f"{ndim}d_{kind}_r{r}", ndim, kind, r)
+        if ndim == 2:
+            interior = (int(rng.integers(200, 700)), int(rng.integers(256, 900)))
+            T = int(rng.integers(3, 40))
+        else:
+            interior = (int(rng.integers(10, 40)), int(rng.integers(64, 100)), int(rng.integers(64, 110)))
+            T = int(rng.integers(2, 9))
+        coeffs = wl.coeffs_for(spec, 100 + g)
+        probs.append(wl.Problem(spec, coeffs, interior, T, field_seed=200 + g, tag=g))
+    return probs
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_batch_equals_single_and_oracle(dtype):
+    import torch
+    probs = _mixed_problems(dtype)
+    fields = [p.field(dtype) for p in probs]
+    xs = [torch.from_numpy(f).cuda() for f in fields]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    status = st.run_batch(probs, xs, ys)
+    assert all(s == st.STENCIL_OK for s in status), status
+    st.stencil_sync(torch.cuda.current_stream().cuda_stream)
+    for p, f, x, y in zip(probs, fields, xs, ys):
+        got = y.cpu().numpy()
+        assert np.array_equal(x.cpu().numpy(), f), "input modified"
+        single = gpu_sweep(p.coeffs, p.spec.r, f, p.T)
+        assert np.array_equal(got, single), (p.spec.name, p.interior, p.T, "batch != single run")
+        ref = oracle.sweep(p.coeffs, p.spec.r, f, p.T)
+        assert np.array_equal(got, ref), (p.spec.name, p.interior, p.T, "batch != oracle")
+
+
+def test_batch_repeat_is_deterministic():
+    import torch
+    probs = _mixed_problems(np.float64, seed=9)[:7]
+    xs = [torch.from_numpy(p.field()).cuda() for p in probs]
+    outs = []
+    for _ in range(2):
+        ys = [torch.empty_like(x) for x in xs]
+        st.run_batch(probs, xs, ys)
+        st.stencil_sync(torch.cuda.current_stream().cuda_stream)
+        outs.append([y.cpu().numpy() for y in ys])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_batch_reports_invalid_jobs():
+    import torch
+    probs = _mixed_problems(np.float64, seed=11)[:3]
+    xs = [torch.from_numpy(p.field()).cuda() for p in probs]
+    ys = [torch.empty_like(x) for x in xs]
+    specs = []
+    for p, x, y in zip(probs, xs, ys):
+        specs.append(dict(coeffs=p.coeffs, radius=p.spec.r, interior=p.interior, dtype=x.dtype,
+                          T=p.T, in_ptr=x.data_ptr(), out_ptr=y.data_ptr()))
+    specs[1]["T"] = -3  # invalid: reported, skipped
+    status = st.stencil_batch_submit(specs, torch.cuda.current_stream().cuda_stream)
+    st.stencil_sync(torch.cuda.current_stream().cuda_stream)
+    assert status[1] == st.STENCIL_ERR_INVALID and status[0] == 0 and status[2] == 0
+    for k in (0, 2):
+        ref = oracle.sweep(probs[k].coeffs, probs[k].spec.r, probs[k].field(), probs[k].T)
+        assert np.array_equal(ys[k].cpu().numpy(), ref)
