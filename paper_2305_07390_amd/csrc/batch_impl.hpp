@@ -49,13 +49,19 @@ __device__ __forceinline__ int find_chunk(const BatchQueue& q, int64_t it) {
 }
 
 // Wait until *ctr >= need. Returns false if the watchdog expired here or an
-// earlier wait of the launch already failed.
+// earlier wait of the launch already failed. Every value that steers the loop
+// is made wave-uniform, so the compiler keeps the persistent item loop around
+// it uniform too (a loop it believed divergent was restructured into a
+// lane-masked one).
 __device__ __forceinline__ bool wait_count(const BatchQueue& q, const unsigned* ctr, unsigned need) {
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   while (true) {
-    const unsigned v = __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned v = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
     if (v >= need) return true;
-    if (__hip_atomic_load(q.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+    const unsigned e = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(q.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (e != 0u) return false;
     if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > q.timeout_ticks) {
       __hip_atomic_store(q.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
@@ -84,10 +90,13 @@ __global__ __launch_bounds__(256) void tb2d_batch_kernel(const Batch2DParams<Rea
   Real* hq = (Real*)lds_raw + (size_t)wid * p.hq_rows * 2 * R;
   const BatchQueue& q = p.q;
   while (true) {
-    unsigned long long it = 0;
-    if (lane == 0) it = atomicAdd(q.cursor, 1ull);
-    const unsigned lo32 = __builtin_amdgcn_readfirstlane((unsigned)(it & 0xffffffffull));
-    const unsigned hi32 = __builtin_amdgcn_readfirstlane((unsigned)(it >> 32));
+    // Claim one item per wave. Every lane executes the atomic (only lane 0
+    // adds 1) and reads lane 0's result: no lane-dependent branch may sit in
+    // this loop, or the optimizer can thread the loop edge on the lane
+    // predicate and send the other lanes around the loop without a claim.
+    const unsigned long long it = atomicAdd(q.cursor, lane == 0 ? 1ull : 0ull);
+    const unsigned lo32 = __builtin_amdgcn_readlane((unsigned)(it & 0xffffffffull), 0);
+    const unsigned hi32 = __builtin_amdgcn_readlane((unsigned)(it >> 32), 0);
     const int64_t item = (int64_t)(((unsigned long long)hi32 << 32) | lo32);
     if (item >= q.nitems) break;
     const int c = find_chunk(q, item);
@@ -96,8 +105,7 @@ __global__ __launch_bounds__(256) void tb2d_batch_kernel(const Batch2DParams<Rea
     const int tile = (int)(item - uni(q.chunk_first[c]));
     const BatchJob2D<Real>& J = p.jobs[job];
     const int tiles = uni(J.tiles);
-    bool ok = true;
-    if (pass > 0) ok = wait_count(q, q.done + job, (unsigned)pass * (unsigned)tiles);
+    const bool ok = pass == 0 || wait_count(q, q.done + job, (unsigned)pass * (unsigned)tiles);
     if (ok) {
       Real wl[KB];
 #pragma unroll
@@ -129,8 +137,10 @@ __global__ __launch_bounds__(256) void tb2d_batch_kernel(const Batch2DParams<Rea
       tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0,
                                           Y1, d);
     }
-    // publish: the release orders this wave's stores before the count
-    if (lane == 0) __hip_atomic_fetch_add(q.done + job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // publish (all lanes execute it, lane 0 counts): the release orders this
+    // wave's stores before the count
+    __hip_atomic_fetch_add(q.done + job, lane == 0 ? 1u : 0u, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -145,10 +155,18 @@ __global__ __launch_bounds__(tb3d::kThreads) void tb3d_batch_kernel(const Batch3
   __shared__ long long s_item;
   __shared__ int s_ok;
   const BatchQueue& q = p.q;
+  const int lane = lane_id();
+  const bool wave0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) == 0;
   while (true) {
-    if (threadIdx.x == 0) s_item = (long long)atomicAdd(q.cursor, 1ull);
+    // wave 0 claims the item (all its lanes execute the atomic, lane 0 adds 1)
+    if (wave0) {
+      const unsigned long long it = atomicAdd(q.cursor, lane == 0 ? 1ull : 0ull);
+      const unsigned lo32 = __builtin_amdgcn_readlane((unsigned)(it & 0xffffffffull), 0);
+      const unsigned hi32 = __builtin_amdgcn_readlane((unsigned)(it >> 32), 0);
+      s_item = (long long)(((unsigned long long)hi32 << 32) | lo32);
+    }
     __syncthreads();
-    const int64_t item = s_item;
+    const int64_t item = uni((int64_t)s_item);
     if (item >= q.nitems) break;
     const int c = find_chunk(q, item);
     const int job = uni(q.chunk_job[c]);
@@ -156,9 +174,9 @@ __global__ __launch_bounds__(tb3d::kThreads) void tb3d_batch_kernel(const Batch3
     const int tile = (int)(item - uni(q.chunk_first[c]));
     const BatchJob3D<Real>& J = p.jobs[job];
     const int tiles = uni(J.tiles);
-    if (threadIdx.x == 0) s_ok = pass > 0 ? (int)wait_count(q, q.done + job, (unsigned)pass * (unsigned)tiles) : 1;
+    if (wave0) s_ok = (pass == 0 || wait_count(q, q.done + job, (unsigned)pass * (unsigned)tiles)) ? 1 : 0;
     __syncthreads();
-    const bool ok = s_ok != 0;
+    const bool ok = __builtin_amdgcn_readfirstlane(s_ok) != 0;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave sees the previous pass
     if (ok) {
       Real wl[KB];
@@ -183,8 +201,9 @@ __global__ __launch_bounds__(tb3d::kThreads) void tb3d_batch_kernel(const Batch3
     // every wave's stores are released before the count is published
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0)
-      __hip_atomic_fetch_add(q.done + job, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (wave0)
+      __hip_atomic_fetch_add(q.done + job, lane == 0 ? 1u : 0u, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
