@@ -61,10 +61,13 @@ typedef struct {
   int64_t n[3];
 } stencil_shape;
 
-/* Optional tuning hint; zero fields mean "choose automatically".
+/* Optional tuning hint; zero fields mean "choose automatically" (from the
+ * autotuner's cache when it holds an entry for this stencil class and size,
+ * else the planner's defaults).
  * depth: time steps fused per pass over HBM (paper Section 6.2).
  * tile[0]: rows (2D) or planes (3D) per streamed segment; tile[1..2] reserved.
- * flags: STENCIL_FLAG_NAIVE forces one plain step per pass. */
+ * flags: STENCIL_FLAG_NAIVE forces one plain step per pass;
+ *        STENCIL_FLAG_NO_CACHE ignores the autotuner's cache. */
 typedef struct {
   int32_t tile[3];
   int32_t depth;
@@ -72,6 +75,7 @@ typedef struct {
 } stencil_tuning;
 
 #define STENCIL_FLAG_NAIVE 1
+#define STENCIL_FLAG_NO_CACHE 2
 
 /* Execution scheme chosen by a plan. */
 typedef enum {
@@ -210,6 +214,53 @@ typedef struct {
 } stencil_model_result;
 
 stencil_status stencil_model_eval(const stencil_model_params* params, stencil_model_result* result);
+
+/* ---- Autotuner (paper Section 3.4: empirical depth search; Sections 5-6:
+ * the model prunes) ----
+ *
+ * stencil_tune times candidate (depth, segment) pairs of the blocked kernel
+ * for this stencil class and grid shape on `stream` and stores the fastest in
+ * a process-wide cache keyed by (gfx arch, CU count, ndim, pattern class,
+ * radius, points, dtype, half-octave size bucket per axis, single or batched).
+ * Candidates: every compiled depth, each with the planner's segment for it and
+ * (single grids) half and double that; candidates whose model rate (cells/s
+ * of valid output, stencil_model_eval with HBM 8 TB/s, one read and one write
+ * per cell and pass, 2k flops per cell and step) is below 60% of the best
+ * model rate are not timed. STENCIL_TUNE_BATCH tunes the depth used by
+ * stencil_batch_submit, timing a batch of replicas of the grid that fills the
+ * device; STENCIL_TUNE_FORCE re-measures a cached entry. The tuner allocates
+ * and frees its own device buffers (in, out(s), workspace of the padded size)
+ * and synchronises `stream`; results never depend on the choice (blocking is
+ * exact). Errors: STENCIL_ERR_INVALID (arguments), STENCIL_ERR_UNSUPPORTED (no
+ * blocked kernel for this stencil and shape), STENCIL_ERR_NOMEM, device errors.
+ *
+ * Plans without a hint and batch jobs with depth 0 use the cached choice.
+ * stencil_tune_lookup reports it (found = 0 when absent); the cache is saved
+ * to and merged from a JSON file ({"entries": [{"key", "depth", "seg", ...}]});
+ * stencil_tune_cache_key writes the key of a request into buf. */
+#define STENCIL_TUNE_BATCH 1
+#define STENCIL_TUNE_FORCE 2
+
+typedef struct {
+  int32_t depth;            /* chosen steps per pass */
+  int32_t seg_len;          /* chosen rows/planes per segment (0: planner's) */
+  double seconds_per_step;  /* measured, per grid */
+  double model_cells_per_s; /* model rate of the chosen candidate */
+  int32_t candidates;       /* candidates timed */
+  int32_t from_cache;       /* 1 if answered from the cache */
+} stencil_tune_result;
+
+stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_shape* shape,
+                            stencil_dtype dtype, int32_t flags, void* stream,
+                            stencil_tune_result* result);
+stencil_status stencil_tune_lookup(const double* coeffs, int32_t radius, const stencil_shape* shape,
+                                   stencil_dtype dtype, int32_t flags, stencil_tuning* out,
+                                   int32_t* found);
+stencil_status stencil_tune_cache_key(const double* coeffs, int32_t radius, const stencil_shape* shape,
+                                      stencil_dtype dtype, int32_t flags, char* buf, size_t len);
+stencil_status stencil_tune_cache_load(const char* path, int32_t* loaded);
+stencil_status stencil_tune_cache_save(const char* path);
+stencil_status stencil_tune_cache_clear(void);
 
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* stencil_last_error(void);

@@ -112,6 +112,15 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     hint.tile[0] = j.shape.ndim == 2 ? kBatchSeg2D : kBatchSeg3D;
     stencil_plan_t pl = nullptr;
     status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+    int tuned_depth = 0, tuned_seg = 0;
+    if (status[i] == STENCIL_OK && j.depth <= 0 &&
+        tune_lookup_plan(pl, true, &tuned_depth, &tuned_seg) && tuned_depth != pl->depth) {
+      // the autotuner's depth for batched tiles of this stencil class and size
+      stencil_plan_destroy(pl);
+      pl = nullptr;
+      hint.depth = tuned_depth;
+      status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+    }
     if (status[i] == STENCIL_OK) {
       const size_t bytes = (size_t)pl->padded_elems * pl->elem;
       const char* a = (const char*)j.in;

@@ -377,6 +377,20 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
   }
 
   const bool force_naive = hint && (hint->flags & STENCIL_FLAG_NAIVE);
+  // without a depth or segment hint, take the autotuner's cached choice
+  stencil_tuning tuned;
+  std::memset(&tuned, 0, sizeof(tuned));
+  const bool use_cache = !(hint && (hint->flags & STENCIL_FLAG_NO_CACHE)) &&
+                         !(hint && (hint->depth > 0 || hint->tile[0] > 0));
+  if (use_cache && T > 0) {
+    int d = 0, seg = 0;
+    if (tune_lookup_plan(p, false, &d, &seg)) {
+      tuned.depth = d;
+      tuned.tile[0] = seg;
+      tuned.flags = hint ? hint->flags : 0;
+      hint = &tuned;
+    }
+  }
   if (T == 0) {
     p->scheme = STENCIL_SCHEME_COPY;
     p->depth = 0;

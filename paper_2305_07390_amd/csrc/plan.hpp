@@ -23,6 +23,12 @@ DeviceInfo device_info();
 
 }  // namespace stencil_impl
 
+struct stencil_plan_s;
+namespace stencil_impl {
+// Autotuner cache lookup for a plan's stencil class and size (tune.cpp).
+bool tune_lookup_plan(const stencil_plan_s* pl, bool batched, int* depth, int* seg);
+}  // namespace stencil_impl
+
 struct stencil_plan_s {
   int ndim = 0;
   int r = 0;

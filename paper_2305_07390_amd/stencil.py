@@ -29,6 +29,12 @@ STENCIL_F32 = 0
 STENCIL_F64 = 1
 
 STENCIL_FLAG_NAIVE = 1
+STENCIL_FLAG_NO_CACHE = 2
+
+STENCIL_TUNE_BATCH = 1
+STENCIL_TUNE_FORCE = 2
+
+TUNE_CACHE_PATH = os.path.join(HERE, "tune_cache.json")
 
 SCHEME_NAMES = {0: "copy", 1: "naive", 2: "blocked_2d", 3: "blocked_3d"}
 PATTERN_NAMES = {0: "star", 1: "box", 2: "general"}
@@ -99,6 +105,12 @@ class stencil_model_result(ctypes.Structure):
                 ("min_tile", ctypes.c_double), ("bottleneck", ctypes.c_int32)]
 
 
+class stencil_tune_result(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("seg_len", ctypes.c_int32),
+                ("seconds_per_step", ctypes.c_double), ("model_cells_per_s", ctypes.c_double),
+                ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+
+
 MODEL_NO_TILING, MODEL_SM_TILING, MODEL_DEVICE_TILING = 0, 1, 2
 
 _P = ctypes.c_void_p
@@ -120,6 +132,17 @@ _SIGNATURES = {
     "stencil_sync": (ctypes.c_int, [_P]),
     "stencil_model_eval": (ctypes.c_int, [ctypes.POINTER(stencil_model_params),
                                            ctypes.POINTER(stencil_model_result)]),
+    "stencil_tune": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape), ctypes.c_int,
+                                     ctypes.c_int32, _P, ctypes.POINTER(stencil_tune_result)]),
+    "stencil_tune_lookup": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape),
+                                            ctypes.c_int, ctypes.c_int32, ctypes.POINTER(stencil_tuning),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "stencil_tune_cache_key": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape),
+                                               ctypes.c_int, ctypes.c_int32, ctypes.c_char_p,
+                                               ctypes.c_size_t]),
+    "stencil_tune_cache_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
+    "stencil_tune_cache_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "stencil_tune_cache_clear": (ctypes.c_int, []),
     "stencil_last_error": (ctypes.c_char_p, []),
 }
 
@@ -241,6 +264,59 @@ def stencil_batch_submit(specs, stream: int = 0):
 
 def stencil_sync(stream: int = 0):
     _check(load_library().stencil_sync(stream or None))
+
+
+def stencil_tune(coeffs, radius: int, interior, dtype, flags: int = 0, stream: int = 0) -> dict:
+    """Autotune (depth, segment) for this stencil class and size; see the header."""
+    c, cp = _coeff_ptr(coeffs)
+    shp = _shape(interior)
+    r = stencil_tune_result()
+    _check(load_library().stencil_tune(cp, int(radius), ctypes.byref(shp), _dtype_code(dtype),
+                                       int(flags), stream or None, ctypes.byref(r)))
+    return {name: getattr(r, name) for name, _ in r._fields_}
+
+
+def stencil_tune_lookup(coeffs, radius: int, interior, dtype, flags: int = 0):
+    """Cached (depth, seg_len) for this request, or None."""
+    c, cp = _coeff_ptr(coeffs)
+    shp = _shape(interior)
+    out = stencil_tuning()
+    found = ctypes.c_int32()
+    _check(load_library().stencil_tune_lookup(cp, int(radius), ctypes.byref(shp), _dtype_code(dtype),
+                                              int(flags), ctypes.byref(out), ctypes.byref(found)))
+    return (out.depth, out.tile[0]) if found.value else None
+
+
+def stencil_tune_cache_key(coeffs, radius: int, interior, dtype, flags: int = 0) -> str:
+    c, cp = _coeff_ptr(coeffs)
+    shp = _shape(interior)
+    buf = ctypes.create_string_buffer(256)
+    _check(load_library().stencil_tune_cache_key(cp, int(radius), ctypes.byref(shp),
+                                                 _dtype_code(dtype), int(flags), buf, 256))
+    return buf.value.decode()
+
+
+def stencil_tune_cache_load(path: str = TUNE_CACHE_PATH) -> int:
+    n = ctypes.c_int32()
+    _check(load_library().stencil_tune_cache_load(path.encode(), ctypes.byref(n)))
+    return n.value
+
+
+def stencil_tune_cache_save(path: str = TUNE_CACHE_PATH):
+    _check(load_library().stencil_tune_cache_save(path.encode()))
+
+
+def stencil_tune_cache_clear():
+    _check(load_library().stencil_tune_cache_clear())
+
+
+def use_tuned_defaults(path: str = TUNE_CACHE_PATH) -> int:
+    """Merge the packaged tuning cache (measured on MI355X) into the library's
+    cache, so that plans without hints use the tuned depths; returns the
+    number of entries (0 if the file is absent)."""
+    if not os.path.exists(path):
+        return 0
+    return stencil_tune_cache_load(path)
 
 
 def run_batch(problems, xs, ys, stream=None, depth=0):
