@@ -262,6 +262,67 @@ stencil_status stencil_tune_cache_load(const char* path, int32_t* loaded);
 stencil_status stencil_tune_cache_save(const char* path);
 stencil_status stencil_tune_cache_clear(void);
 
+/* ---- Serving loop (continuous batching of stencil requests) ----
+ *
+ * A server owns one HIP device, a compute stream, a copy stream and a
+ * scheduler thread. Requests (a stencil_job whose in/out are ignored, plus the
+ * padded input grid in host memory, copied at submit so the caller may reuse
+ * it) wait in a FIFO queue. Admission: a request enters when a slot is free
+ * and the device memory it needs (two padded grids plus the batch workspace,
+ * held until its result is collected) fits in the HBM budget; the input is
+ * copied to the device on the copy stream while the current round runs. Each
+ * round runs the next quantum (at most quantum_passes passes of the request's
+ * temporal depth) of every resident request in one stencil_batch_submit, so a
+ * request that arrives mid-round starts at the next round and its work shares
+ * the device with the others'. Latency is measured from submit to the end of
+ * the round that completes the request; results stay on the device until
+ * stencil_server_poll collects them. Results equal stencil_run's bit for bit
+ * (running T steps as several quanta is the same arithmetic).
+ *
+ * stencil_server_create: budget > 0, max_slots >= 1; quantum_passes <= 0
+ *   means 4. Fails with STENCIL_ERR_DEVICE when the device is unusable.
+ * stencil_server_submit: STENCIL_ERR_BUDGET if the request alone exceeds the
+ *   budget, STENCIL_ERR_INVALID for a bad job (as stencil_plan) or NULL
+ *   arguments; otherwise returns a ticket.
+ * stencil_server_poll: *done = 0 while pending; once done, copies the padded
+ *   result to host_out (if not NULL), stores the latency, releases the
+ *   request's device memory and forgets the ticket (*done = 1). Returns the
+ *   request's own error (e.g. STENCIL_ERR_TIMEOUT) if it failed, and
+ *   STENCIL_ERR_INVALID for an unknown ticket. stencil_server_wait blocks
+ *   until the request is done, then behaves like poll.
+ * stencil_server_stats: counters and latency percentiles over the requests
+ *   completed so far (nearest-rank p50 / p99).
+ * stencil_server_destroy: stops the scheduler after the round in flight,
+ *   drops pending requests and releases all device memory. */
+typedef struct stencil_server_s* stencil_server_t;
+
+typedef struct {
+  int32_t device;            /* HIP device ordinal */
+  int32_t max_slots;         /* resident requests at most */
+  int32_t quantum_passes;    /* passes per request per round (<= 0: 4) */
+  uint64_t hbm_budget_bytes; /* device memory for resident requests */
+} stencil_server_config;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, failed, rejected, rounds;
+  int32_t active, queued, max_active;
+  uint64_t hbm_in_use, hbm_peak;
+  double cell_updates;       /* completed requests' cells x T */
+  double busy_s;             /* rounds' device time */
+  double wall_s;             /* first submit to last completion */
+  double p50_s, p99_s, mean_s, max_s; /* latency of completed requests */
+} stencil_server_statistics;
+
+stencil_status stencil_server_create(const stencil_server_config* config, stencil_server_t* server);
+stencil_status stencil_server_submit(stencil_server_t server, const stencil_job* job,
+                                     const void* host_in, uint64_t* ticket);
+stencil_status stencil_server_poll(stencil_server_t server, uint64_t ticket, void* host_out,
+                                   int32_t* done, double* latency_s);
+stencil_status stencil_server_wait(stencil_server_t server, uint64_t ticket, void* host_out,
+                                   double* latency_s);
+stencil_status stencil_server_stats(stencil_server_t server, stencil_server_statistics* stats);
+stencil_status stencil_server_destroy(stencil_server_t server);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* stencil_last_error(void);
 

@@ -1,28 +1,31 @@
 // Batch dispatch and the batched halo-frame copy.
 #include "device_common.hpp"
 #include "launch.hpp"
+#include "batch_impl.hpp"
 
 namespace stencil_impl {
 
-hipError_t tb2d_batch_launch_f64(int r, int shape, const void* params, int grid, size_t lds, hipStream_t s);
-hipError_t tb2d_batch_launch_f32(int r, int shape, const void* params, int grid, size_t lds, hipStream_t s);
-hipError_t tb3d_batch_launch_f64(int r, int shape, const void* params, int grid, hipStream_t s);
-hipError_t tb3d_batch_launch_f32(int r, int shape, const void* params, int grid, hipStream_t s);
+hipError_t batch_launch_f64(const void* params, int grid, size_t lds, hipStream_t s);
+hipError_t batch_launch_f32(const void* params, int grid, size_t lds, hipStream_t s);
 
-hipError_t tb2d_batch_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
-                             size_t lds_bytes, hipStream_t stream) {
-  (void)depth;  // each job carries its depths; the kernel holds the deepest
-  if (dtype == kF64) return tb2d_batch_launch_f64(r, shape, params, grid, lds_bytes, stream);
-  if (dtype == kF32) return tb2d_batch_launch_f32(r, shape, params, grid, lds_bytes, stream);
+hipError_t batch_launch(int dtype, const void* params, int grid, size_t lds_bytes, hipStream_t stream) {
+  if (dtype == kF64) return batch_launch_f64(params, grid, lds_bytes, stream);
+  if (dtype == kF32) return batch_launch_f32(params, grid, lds_bytes, stream);
   return hipErrorInvalidValue;
 }
 
-hipError_t tb3d_batch_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
-                             hipStream_t stream) {
-  (void)depth;
-  if (dtype == kF64) return tb3d_batch_launch_f64(r, shape, params, grid, stream);
-  if (dtype == kF32) return tb3d_batch_launch_f32(r, shape, params, grid, stream);
-  return hipErrorInvalidValue;
+int batch_max_depth(int dtype, int ndim, int r, int shape) {
+  if (r < 1 || r > kMaxR || shape < kStar || shape > kGeneral) return 0;
+  if (ndim == 3 && r > 2) return 0;
+  if (ndim != 2 && ndim != 3) return 0;
+  return batch::batch_depth_c(dtype, ndim, r, shape);
+}
+
+size_t batch_lds_3d(int dtype, int r) {
+  const bool f64 = dtype == kF64;
+  if (r == 1) return f64 ? tb3d::Lds<double, 1>::kBytes : tb3d::Lds<float, 1>::kBytes;
+  if (r == 2) return f64 ? tb3d::Lds<double, 2>::kBytes : tb3d::Lds<float, 2>::kBytes;
+  return 0;
 }
 
 namespace {

@@ -2,11 +2,11 @@
 //
 // Every job is planned like a single grid, with longer tiles so that small
 // grids are not cut into slivers. Jobs with a blocked variant are grouped by
-// kernel variant (dimension, dtype, radius, pattern); each group becomes one
-// persistent launch over a work list of (job, pass) chunks ordered by the
-// fraction of the job completed after the chunk, so that long and short jobs
-// progress together and finish together. Device memory for workspaces, job
-// descriptors, the work list and counters is one stream-ordered allocation.
+// dtype; each group becomes one persistent launch of the fused batch kernel
+// over a work list of (job, pass) chunks ordered by the fraction of the job
+// completed after the chunk, so that long and short jobs progress together
+// and finish together. Device memory for workspaces, job descriptors, the
+// work list and counters is one stream-ordered allocation.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,9 +44,14 @@ unsigned int* device_error_word() {
 }
 
 struct Group {
-  int ndim, dtype, r, pattern;
+  int dtype;
   std::vector<int> jobs;  // indices into the batch
 };
+
+// Work-list items of one pass: a 3D tile, or up to four 2D wave tiles.
+int64_t items_per_pass(const stencil_plan_s* p) {
+  return p->ndim == 2 ? (p->tiles + 3) / 4 : p->tiles;
+}
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -72,20 +77,38 @@ void build_worklist(const std::vector<stencil_plan_s*>& plans, const std::vector
   for (const C& c : chunks) {
     cj.push_back(c.job);
     cp.push_back(c.pass);
-    cf.push_back(cf.back() + plans[members[c.job]]->tiles);
+    cf.push_back(cf.back() + items_per_pass(plans[members[c.job]]));
   }
 }
 
-template <typename Job, typename Real>
-void fill_common(Job& J, const stencil_plan_s* p, const void* in, void* out, void* ws) {
+template <typename Real>
+BatchJob<Real> make_job(const stencil_plan_s* p, const void* in, void* out, void* ws) {
+  BatchJob<Real> J;
+  std::memset(&J, 0, sizeof(J));
   J.in = in;
   J.out = out;
   J.ws = ws;
+  J.variant = batch_variant(p->ndim, p->r, p->pattern);
+  J.tiles = p->tiles;
   J.npass = (int32_t)p->pass_depth.size();
   J.depth = p->pass_depth.front();
   J.depth_last = p->pass_depth.back();
+  J.P = p->ext[2];
+  J.Qy = p->ext[1];
+  J.Qz = p->ext[0];
+  J.seg_len = p->seg_len;
+  if (p->ndim == 2) {
+    J.strips = p->strips;
+    J.hl = p->hl;
+  } else {
+    J.sx = p->sx;
+    J.sy = p->sy;
+    J.hx = p->hx;
+    J.hy = p->hy;
+  }
   const size_t nw = std::min(p->coeffs.size(), sizeof(J.w) / sizeof(J.w[0]));
   for (size_t i = 0; i < nw; ++i) J.w[i] = (Real)p->coeffs[i];
+  return J;
 }
 
 }  // namespace
@@ -120,6 +143,24 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
       pl = nullptr;
       hint.depth = tuned_depth;
       status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+    }
+    if (status[i] == STENCIL_OK &&
+        (pl->scheme == STENCIL_SCHEME_BLOCKED_2D || pl->scheme == STENCIL_SCHEME_BLOCKED_3D)) {
+      // the fused batch kernel's own depth limit for this variant
+      const int cap = batch_max_depth(pl->dtype == STENCIL_F64 ? kF64 : kF32, pl->ndim, pl->r,
+                                      pl->pattern);
+      if (pl->depth > cap) {
+        stencil_plan_destroy(pl);
+        pl = nullptr;
+        hint.depth = cap;
+        if (cap > 0) status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+        if (cap <= 0 || status[i] != STENCIL_OK) {
+          // no batched variant: plan for the plain path
+          hint.depth = 0;
+          hint.flags = STENCIL_FLAG_NAIVE;
+          status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+        }
+      }
     }
     if (status[i] == STENCIL_OK) {
       const size_t bytes = (size_t)pl->padded_elems * pl->elem;
@@ -158,24 +199,20 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
   for (int i = 0; i < n; ++i) valid += plans[i] != nullptr;
   if (!valid) return fail(STENCIL_ERR_INVALID, "no valid job in the batch");
 
-  // groups of blocked jobs by kernel variant; everything else runs alone
-  std::map<std::tuple<int, int, int, int>, Group> groups;
+  // groups of blocked jobs by dtype; everything else runs alone
+  Group groups[2];
+  groups[kF32].dtype = kF32;
+  groups[kF64].dtype = kF64;
   std::vector<int> alone;
   for (int i = 0; i < n; ++i) {
     stencil_plan_s* p = plans[i];
     if (!p) continue;
-    if (p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D) {
-      const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
-      auto key = std::make_tuple(p->ndim, dt, p->r, p->pattern);
-      Group& g = groups[key];
-      g.ndim = p->ndim;
-      g.dtype = dt;
-      g.r = p->r;
-      g.pattern = p->pattern;
-      g.jobs.push_back(i);
-    } else {
+    const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
+    const bool blocked = p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D;
+    if (blocked && p->depth <= batch_max_depth(dt, p->ndim, p->r, p->pattern))
+      groups[dt].jobs.push_back(i);
+    else
       alone.push_back(i);
-    }
   }
 
   // device memory: workspaces, then per-group control blocks, then frame-copy lists
@@ -187,19 +224,20 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     total = align256(total + plans[i]->workspace);
   }
   struct GroupMem {
-    size_t jobs_off, cj_off, cp_off, cf_off, cursor_off, done_off;
+    size_t jobs_off = 0, cj_off = 0, cp_off = 0, cf_off = 0, cursor_off = 0, done_off = 0;
     std::vector<int32_t> cj, cp;
     std::vector<int64_t> cf;
-    int hq_rows = 0;
+    int64_t hq_stride = 0;  // LDS halo elements per wave (2D jobs)
+    size_t lds = 0;
   };
-  std::vector<GroupMem> gmem;
-  std::vector<Group*> glist;
-  for (auto& kv : groups) {
-    Group& g = kv.second;
-    GroupMem m;
+  GroupMem gmem[2];
+  for (int d = 0; d < 2; ++d) {
+    Group& g = groups[d];
+    if (g.jobs.empty()) continue;
+    GroupMem& m = gmem[d];
     build_worklist(plans, g.jobs, m.cj, m.cp, m.cf);
-    const size_t job_sz = g.ndim == 2 ? (g.dtype == kF64 ? sizeof(BatchJob2D<double>) : sizeof(BatchJob2D<float>))
-                                      : (g.dtype == kF64 ? sizeof(BatchJob3D<double>) : sizeof(BatchJob3D<float>));
+    const size_t job_sz = d == kF64 ? sizeof(BatchJob<double>) : sizeof(BatchJob<float>);
+    const size_t elem = d == kF64 ? 8 : 4;
     m.jobs_off = total;
     total = align256(total + job_sz * g.jobs.size());
     m.cj_off = total;
@@ -212,26 +250,29 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     total = align256(total + 8);
     m.done_off = total;
     total = align256(total + 4 * g.jobs.size());
-    for (int i : g.jobs) m.hq_rows = std::max(m.hq_rows, plans[i]->hq_rows);
-    gmem.push_back(std::move(m));
-    glist.push_back(&g);
+    for (int i : g.jobs) {
+      const stencil_plan_s* p = plans[i];
+      if (p->ndim == 2) m.hq_stride = std::max<int64_t>(m.hq_stride, (int64_t)p->hq_rows * 2 * p->r);
+      else m.lds = std::max(m.lds, batch_lds_3d(d, p->r));
+    }
+    m.lds = std::max(m.lds, (size_t)(4 * m.hq_stride) * elem);
   }
   std::vector<FrameCopyJob> frames[2];  // per dtype
-  for (auto* g : glist)
-    for (int i : g->jobs) {
+  for (int d = 0; d < 2; ++d)
+    for (int i : groups[d].jobs) {
       const stencil_plan_s* p = plans[i];
       FrameCopyJob f;
       std::memset(&f, 0, sizeof(f));
       f.src = jobs[i].in;
-      for (int d = 0; d < 3; ++d) {
-        f.ext[d] = p->ext[d];
-        f.r[d] = p->rad[d];
+      for (int k = 0; k < 3; ++k) {
+        f.ext[k] = p->ext[k];
+        f.r[k] = p->rad[k];
       }
       f.dst = jobs[i].out;
-      frames[g->dtype].push_back(f);
+      frames[d].push_back(f);
       if (p->workspace) {
         f.dst = nullptr;  // filled once the block address is known
-        frames[g->dtype].push_back(f);
+        frames[d].push_back(f);
       }
     }
   size_t frames_off[2];
@@ -239,8 +280,11 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     frames_off[d] = total;
     total = align256(total + sizeof(FrameCopyJob) * frames[d].size());
   }
-  const size_t ctl_begin = 0;
-  (void)ctl_begin;
+  for (int d = 0; d < 2; ++d)
+    if (gmem[d].lds > (size_t)160 * 1024) {
+      for (auto* p : plans) stencil_plan_destroy(p);
+      return fail(STENCIL_ERR_UNSUPPORTED, "batch needs %zu bytes of LDS per workgroup", gmem[d].lds);
+    }
 
   char* dev = nullptr;
   if (total) {
@@ -258,63 +302,33 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     return fail(STENCIL_ERR_NOMEM, "device error word allocation failed");
   }
 
-  // host image of the control region (everything after the first workspace
-  // bytes is small); counters start at zero
+  // host image of the control region (everything after the workspaces is
+  // small); counters start at zero
   size_t ctl_lo = total;
-  for (auto& m : gmem) ctl_lo = std::min(ctl_lo, m.jobs_off);
-  for (int d = 0; d < 2; ++d) ctl_lo = std::min(ctl_lo, frames_off[d]);
+  for (int d = 0; d < 2; ++d) {
+    if (!groups[d].jobs.empty()) ctl_lo = std::min(ctl_lo, gmem[d].jobs_off);
+    ctl_lo = std::min(ctl_lo, frames_off[d]);
+  }
   std::vector<char> img(total - ctl_lo, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(img.data() + (off - ctl_lo), src, bytes);
   };
-  for (size_t gi = 0; gi < glist.size(); ++gi) {
-    Group& g = *glist[gi];
-    GroupMem& m = gmem[gi];
+  for (int d = 0; d < 2; ++d) {
+    Group& g = groups[d];
+    GroupMem& m = gmem[d];
     for (size_t local = 0; local < g.jobs.size(); ++local) {
       const int i = g.jobs[local];
       const stencil_plan_s* p = plans[i];
       void* ws = p->workspace ? (void*)(dev + ws_off[i]) : nullptr;
-      if (g.ndim == 2) {
-        auto fill2 = [&](auto* proto) {
-          using J = std::remove_pointer_t<decltype(proto)>;
-          J jd;
-          std::memset(&jd, 0, sizeof(jd));
-          using Real = std::remove_reference_t<decltype(jd.w[0])>;
-          fill_common<J, Real>(jd, p, jobs[i].in, jobs[i].out, ws);
-          jd.P = p->ext[2];
-          jd.Q = p->ext[1];
-          jd.strips = p->strips;
-          jd.segs = p->segs;
-          jd.seg_len = p->seg_len;
-          jd.tiles = p->tiles;
-          jd.hl = p->hl;
-          put(m.jobs_off + local * sizeof(J), &jd, sizeof(J));
-        };
-        if (g.dtype == kF64) fill2((BatchJob2D<double>*)nullptr);
-        else fill2((BatchJob2D<float>*)nullptr);
+      if (d == kF64) {
+        const BatchJob<double> J = make_job<double>(p, jobs[i].in, jobs[i].out, ws);
+        put(m.jobs_off + local * sizeof(J), &J, sizeof(J));
       } else {
-        auto fill3 = [&](auto* proto) {
-          using J = std::remove_pointer_t<decltype(proto)>;
-          J jd;
-          std::memset(&jd, 0, sizeof(jd));
-          using Real = std::remove_reference_t<decltype(jd.w[0])>;
-          fill_common<J, Real>(jd, p, jobs[i].in, jobs[i].out, ws);
-          jd.P = p->ext[2];
-          jd.Qy = p->ext[1];
-          jd.Qz = p->ext[0];
-          jd.sx = p->sx;
-          jd.sy = p->sy;
-          jd.segs = p->segs;
-          jd.seg_len = p->seg_len;
-          jd.tiles = p->tiles;
-          jd.hx = p->hx;
-          jd.hy = p->hy;
-          put(m.jobs_off + local * sizeof(J), &jd, sizeof(J));
-        };
-        if (g.dtype == kF64) fill3((BatchJob3D<double>*)nullptr);
-        else fill3((BatchJob3D<float>*)nullptr);
+        const BatchJob<float> J = make_job<float>(p, jobs[i].in, jobs[i].out, ws);
+        put(m.jobs_off + local * sizeof(J), &J, sizeof(J));
       }
     }
+    if (g.jobs.empty()) continue;
     put(m.cj_off, m.cj.data(), 4 * m.cj.size());
     put(m.cp_off, m.cp.data(), 4 * m.cp.size());
     put(m.cf_off, m.cf.data(), 8 * m.cf.size());
@@ -322,12 +336,9 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
   for (int d = 0; d < 2; ++d) {
     // second entry of a pair targets the job's workspace
     size_t k = 0;
-    for (auto* g : glist) {
-      if (g->dtype != d) continue;
-      for (int i : g->jobs) {
-        ++k;  // the `out` entry
-        if (plans[i]->workspace) frames[d][k++].dst = dev + ws_off[i];
-      }
+    for (int i : groups[d].jobs) {
+      ++k;  // the `out` entry
+      if (plans[i]->workspace) frames[d][k++].dst = dev + ws_off[i];
     }
     put(frames_off[d], frames[d].data(), sizeof(FrameCopyJob) * frames[d].size());
   }
@@ -342,9 +353,10 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     e = frame_copy_batch_launch(d, (const FrameCopyJob*)(dev + frames_off[d]), (int)frames[d].size(), s);
     if (e != hipSuccess) st = hip_fail(e, "batch halo copy");
   }
-  for (size_t gi = 0; gi < glist.size() && st == STENCIL_OK; ++gi) {
-    Group& g = *glist[gi];
-    GroupMem& m = gmem[gi];
+  for (int d = 0; d < 2 && st == STENCIL_OK; ++d) {
+    Group& g = groups[d];
+    if (g.jobs.empty()) continue;
+    GroupMem& m = gmem[d];
     BatchQueue q;
     q.chunk_job = (const int32_t*)(dev + m.cj_off);
     q.chunk_pass = (const int32_t*)(dev + m.cp_off);
@@ -355,24 +367,14 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     q.done = (unsigned int*)(dev + m.done_off);
     q.err = err;
     q.timeout_ticks = kTimeoutTicks;
-    if (g.ndim == 2) {
-      const size_t elem = g.dtype == kF64 ? 8 : 4;
-      const size_t lds = (size_t)4 * m.hq_rows * 2 * g.r * elem;
-      if (g.dtype == kF64) {
-        Batch2DParams<double> prm{(const BatchJob2D<double>*)(dev + m.jobs_off), q, m.hq_rows};
-        e = tb2d_batch_launch(g.dtype, g.r, g.pattern, 0, &prm, cus, lds, s);
-      } else {
-        Batch2DParams<float> prm{(const BatchJob2D<float>*)(dev + m.jobs_off), q, m.hq_rows};
-        e = tb2d_batch_launch(g.dtype, g.r, g.pattern, 0, &prm, cus, lds, s);
-      }
+    // one workgroup per CU, never more than there are items
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, q.nitems));
+    if (d == kF64) {
+      BatchParams<double> prm{(const BatchJob<double>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
+      e = batch_launch(d, &prm, grid, m.lds, s);
     } else {
-      if (g.dtype == kF64) {
-        Batch3DParams<double> prm{(const BatchJob3D<double>*)(dev + m.jobs_off), q};
-        e = tb3d_batch_launch(g.dtype, g.r, g.pattern, 0, &prm, cus, s);
-      } else {
-        Batch3DParams<float> prm{(const BatchJob3D<float>*)(dev + m.jobs_off), q};
-        e = tb3d_batch_launch(g.dtype, g.r, g.pattern, 0, &prm, cus, s);
-      }
+      BatchParams<float> prm{(const BatchJob<float>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
+      e = batch_launch(d, &prm, grid, m.lds, s);
     }
     if (e != hipSuccess) st = hip_fail(e, "batch launch");
   }

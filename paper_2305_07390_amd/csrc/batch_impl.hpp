@@ -2,16 +2,17 @@
 //
 // The decomposition of each grid is the single-grid one (tb2d / tb3d tiles);
 // what changes is the schedule (the paper's tile-by-tile execution, Section
-// 4.1, extended to a work list): a fixed set of workgroups pulls (job, pass,
-// tile) items from one counter, waits until the job's previous pass is
-// complete, runs the tile and publishes its completion. Waits are bounded by
-// a realtime-clock watchdog; an expired wait sets an error word, and every
-// later item of the launch skips its work so the launch still drains.
+// 4.1, extended to a work list): one workgroup per CU pulls (job, pass, tiles)
+// items of every grid and stencil variant of a dtype from one counter, waits
+// until the job's previous pass is complete, runs the tiles and publishes
+// their completion. Waits are bounded by a realtime-clock watchdog; an expired
+// wait sets an error word, and every later item of the launch skips its work
+// so the launch still drains.
 #pragma once
 #include "tb2d_impl.hpp"
 #include "tb3d_impl.hpp"
 
-// Host launchers, one translation unit per (dimension, dtype); see batch*.hip.
+// One translation unit per dtype instantiates the kernel; see batch_f*.hip.
 
 namespace stencil_impl {
 namespace batch {
@@ -79,86 +80,101 @@ __device__ __forceinline__ void pass_buffers(const void* in, void* out, void* ws
   *dst = ((npass - 1 - pass) & 1) == 0 ? out : ws;
 }
 
-template <typename Real, int R, int SHAPE, int DEPTH>
-__global__ __launch_bounds__(256) void tb2d_batch_kernel(const Batch2DParams<Real> p) {
-  constexpr int V = ColsPerLane<Real>::value;
-  constexpr int W = kWave * V;
-  constexpr int KB = (2 * R + 1) * (2 * R + 1);
-  extern __shared__ char lds_raw[];
-  const int lane = lane_id();
-  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-  Real* hq = (Real*)lds_raw + (size_t)wid * p.hq_rows * 2 * R;
-  const BatchQueue& q = p.q;
-  while (true) {
-    // Claim one item per wave. Every lane executes the atomic (only lane 0
-    // adds 1) and reads lane 0's result: no lane-dependent branch may sit in
-    // this loop, or the optimizer can thread the loop edge on the lane
-    // predicate and send the other lanes around the loop without a claim.
-    const unsigned long long it = atomicAdd(q.cursor, lane == 0 ? 1ull : 0ull);
-    const unsigned lo32 = __builtin_amdgcn_readlane((unsigned)(it & 0xffffffffull), 0);
-    const unsigned hi32 = __builtin_amdgcn_readlane((unsigned)(it >> 32), 0);
-    const int64_t item = (int64_t)(((unsigned long long)hi32 << 32) | lo32);
-    if (item >= q.nitems) break;
-    const int c = find_chunk(q, item);
-    const int job = uni(q.chunk_job[c]);
-    const int pass = uni(q.chunk_pass[c]);
-    const int tile = (int)(item - uni(q.chunk_first[c]));
-    const BatchJob2D<Real>& J = p.jobs[job];
-    const int tiles = uni(J.tiles);
-    const bool ok = pass == 0 || wait_count(q, q.done + job, (unsigned)pass * (unsigned)tiles);
-    if (ok) {
-      Real wl[KB];
+// Deepest compiled depth of a batched variant. All variants share one kernel
+// (and so one register allocation), where radius-2 star tiles at depth 8
+// spill; they stop at 7 there.
+constexpr int batch_depth_c(int dtype, int ndim, int r, int shape) {
+  return ndim == 2 ? ((r == 2 && shape == kStar) ? 7 : max_depth_c(r, shape))
+                   : tb3d::max_depth_c(dtype, r, shape);
+}
+
+// One wave tile of a 2D job (the tb2d strip/segment decomposition).
+template <typename Real, int R, int SHAPE>
+__device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int tile, Real* hq, int lane) {
+  constexpr int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 2, R, SHAPE);
+  if constexpr (DEPTH > 0) {
+    constexpr int V = ColsPerLane<Real>::value;
+    constexpr int W = kWave * V;
+    constexpr int KB = (2 * R + 1) * (2 * R + 1);
+    Real wl[KB];
 #pragma unroll
-      for (int k = 0; k < KB; ++k) wl[k] = uni(J.w[k]);
-      const void* in = uni_ptr(J.in);
-      const int npass = uni(J.npass);
-      const void* src;
-      void* dst;
-      pass_buffers(in, uni_ptr(J.out), uni_ptr(J.ws), npass, pass, &src, &dst);
-      const int d = pass == npass - 1 ? uni(J.depth_last) : uni(J.depth);
-      const int P = (int)uni(J.P), Q = (int)uni(J.Q);
-      const int ns = uni(J.strips), HL = uni(J.hl), seg_len = uni(J.seg_len);
-      const int seg = tile / ns;
-      const int strip = tile - seg * ns;
-      const int Y0 = seg * seg_len;
-      const int Y1 = (Y0 + seg_len < Q) ? Y0 + seg_len : Q;
-      int edge, X0, la, lb;
-      if (ns == 1) {
-        edge = kBothEdges; X0 = R; la = 0; lb = kWave;
-      } else if (strip == 0) {
-        edge = kLeftEdge; X0 = R; la = 0; lb = kWave - HL;
-      } else if (strip == ns - 1) {
-        edge = kRightEdge; X0 = P - R - W; la = HL; lb = kWave;
-      } else {
-        edge = kInterior;
-        X0 = R + (kWave - HL) * V + (strip - 1) * (kWave - 2 * HL) * V - HL * V;
-        la = HL; lb = kWave - HL;
-      }
-      tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0,
-                                          Y1, d);
+    for (int k = 0; k < KB; ++k) wl[k] = uni(J.w[k]);
+    const void* in = uni_ptr(J.in);
+    const int npass = uni(J.npass);
+    const void* src;
+    void* dst;
+    pass_buffers(in, uni_ptr(J.out), uni_ptr(J.ws), npass, pass, &src, &dst);
+    const int d = pass == npass - 1 ? uni(J.depth_last) : uni(J.depth);
+    const int P = (int)uni(J.P), Q = (int)uni(J.Qy);
+    const int ns = uni(J.strips), HL = uni(J.hl), seg_len = uni(J.seg_len);
+    const int seg = tile / ns;
+    const int strip = tile - seg * ns;
+    const int Y0 = seg * seg_len;
+    const int Y1 = (Y0 + seg_len < Q) ? Y0 + seg_len : Q;
+    int edge, X0, la, lb;
+    if (ns == 1) {
+      edge = kBothEdges; X0 = R; la = 0; lb = kWave;
+    } else if (strip == 0) {
+      edge = kLeftEdge; X0 = R; la = 0; lb = kWave - HL;
+    } else if (strip == ns - 1) {
+      edge = kRightEdge; X0 = P - R - W; la = HL; lb = kWave;
+    } else {
+      edge = kInterior;
+      X0 = R + (kWave - HL) * V + (strip - 1) * (kWave - 2 * HL) * V - HL * V;
+      la = HL; lb = kWave - HL;
     }
-    // publish (all lanes execute it, lane 0 counts): the release orders this
-    // wave's stores before the count
-    __hip_atomic_fetch_add(q.done + job, lane == 0 ? 1u : 0u, __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0, Y1, d);
   }
 }
 
-template <typename Real, int R, int SHAPE, int DEPTH>
-__global__ __launch_bounds__(tb3d::kThreads) void tb3d_batch_kernel(const Batch3DParams<Real> p) {
-  using namespace tb3d;
-  using FL = FaceLayout<R>;
-  constexpr int KB = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+// One workgroup tile of a 3D job (the tb3d xy-tile/z-segment decomposition).
+template <typename Real, int R, int SHAPE>
+__device__ __forceinline__ void run_3d(const BatchJob<Real>& J, int pass, int tile, char* lds) {
+  constexpr int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 3, R, SHAPE);
+  if constexpr (DEPTH > 0) {
+    using namespace tb3d;
+    using FL = FaceLayout<R>;
+    constexpr int KB = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+    Real* faces = (Real*)lds;
+    Real* xchg = faces + kRing * FL::kPerPlane;
+    Real wl[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) wl[k] = uni(J.w[k]);
+    const int npass = uni(J.npass);
+    const void* src;
+    void* dst;
+    pass_buffers(uni_ptr(J.in), uni_ptr(J.out), uni_ptr(J.ws), npass, pass, &src, &dst);
+    const int d = pass == npass - 1 ? uni(J.depth_last) : uni(J.depth);
+    const int P = (int)uni(J.P), Qy = (int)uni(J.Qy), Qz = (int)uni(J.Qz);
+    const int sx = uni(J.sx), sy = uni(J.sy), seg_len = uni(J.seg_len);
+    const int seg = tile / (sx * sy);
+    const int rem = tile - seg * sx * sy;
+    const int ty = rem / sx;
+    const int tx = rem - ty * sx;
+    const Tb3dGeom g = tb3d_geom<R>(tx, ty, sx, sy, P, Qy, uni(J.hx), uni(J.hy));
+    const int Zs0 = seg * seg_len;
+    const int Zs1 = (Zs0 + seg_len < Qz) ? Zs0 + seg_len : Qz;
+    tb3d_tile<Real, R, SHAPE, DEPTH>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, d, faces, xchg);
+  }
+}
+
+// The persistent batch kernel of one dtype: every compiled 2D and 3D variant
+// behind one work list. A workgroup claims an item (a 3D tile, or up to four
+// 2D tiles of one pass, one per wave), waits for the job's previous pass, runs
+// it and publishes the tiles done. Loop control is workgroup-uniform: wave 0
+// claims and waits, the result travels through LDS behind a barrier, and no
+// lane-dependent branch sits in the loop (the optimizer may thread a loop edge
+// on such a predicate and skip the claim).
+template <typename Real>
+__global__ __launch_bounds__(256) void batch_kernel(const BatchParams<Real> p) {
   extern __shared__ char lds_raw[];
-  Real* faces = (Real*)lds_raw;
-  Real* xchg = faces + kRing * FL::kPerPlane;
   __shared__ long long s_item;
   __shared__ int s_ok;
   const BatchQueue& q = p.q;
   const int lane = lane_id();
-  const bool wave0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)) == 0;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const bool wave0 = wid == 0;
   while (true) {
-    // wave 0 claims the item (all its lanes execute the atomic, lane 0 adds 1)
     if (wave0) {
       const unsigned long long it = atomicAdd(q.cursor, lane == 0 ? 1ull : 0ull);
       const unsigned lo32 = __builtin_amdgcn_readlane((unsigned)(it & 0xffffffffull), 0);
@@ -171,38 +187,49 @@ __global__ __launch_bounds__(tb3d::kThreads) void tb3d_batch_kernel(const Batch3
     const int c = find_chunk(q, item);
     const int job = uni(q.chunk_job[c]);
     const int pass = uni(q.chunk_pass[c]);
-    const int tile = (int)(item - uni(q.chunk_first[c]));
-    const BatchJob3D<Real>& J = p.jobs[job];
+    const int sub = (int)(item - uni(q.chunk_first[c]));
+    const BatchJob<Real>& J = p.jobs[job];
+    const int variant = uni(J.variant);
     const int tiles = uni(J.tiles);
     if (wave0) s_ok = (pass == 0 || wait_count(q, q.done + job, (unsigned)pass * (unsigned)tiles)) ? 1 : 0;
     __syncthreads();
     const bool ok = __builtin_amdgcn_readfirstlane(s_ok) != 0;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave sees the previous pass
-    if (ok) {
-      Real wl[KB];
-#pragma unroll
-      for (int k = 0; k < KB; ++k) wl[k] = uni(J.w[k]);
-      const int npass = uni(J.npass);
-      const void* src;
-      void* dst;
-      pass_buffers(uni_ptr(J.in), uni_ptr(J.out), uni_ptr(J.ws), npass, pass, &src, &dst);
-      const int d = pass == npass - 1 ? uni(J.depth_last) : uni(J.depth);
-      const int P = (int)uni(J.P), Qy = (int)uni(J.Qy), Qz = (int)uni(J.Qz);
-      const int sx = uni(J.sx), sy = uni(J.sy), seg_len = uni(J.seg_len);
-      const int seg = tile / (sx * sy);
-      const int rem = tile - seg * sx * sy;
-      const int ty = rem / sx;
-      const int tx = rem - ty * sx;
-      const Tb3dGeom g = tb3d_geom<R>(tx, ty, sx, sy, P, Qy, uni(J.hx), uni(J.hy));
-      const int Zs0 = seg * seg_len;
-      const int Zs1 = (Zs0 + seg_len < Qz) ? Zs0 + seg_len : Qz;
-      tb3d_tile<Real, R, SHAPE, DEPTH>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, d, faces, xchg);
+    unsigned ndone = 1;
+    if (variant < kBatch3DBase) {
+      const int first = 4 * sub;
+      ndone = (unsigned)((tiles - first) < 4 ? (tiles - first) : 4);
+      const int t = first + wid;
+      if (ok && t < tiles) {
+        Real* hq = (Real*)lds_raw + (size_t)wid * p.hq_stride;
+        switch (variant) {
+          case batch_variant(2, 1, kStar): run_2d<Real, 1, kStar>(J, pass, t, hq, lane); break;
+          case batch_variant(2, 1, kBox): run_2d<Real, 1, kBox>(J, pass, t, hq, lane); break;
+          case batch_variant(2, 1, kGeneral): run_2d<Real, 1, kGeneral>(J, pass, t, hq, lane); break;
+          case batch_variant(2, 2, kStar): run_2d<Real, 2, kStar>(J, pass, t, hq, lane); break;
+          case batch_variant(2, 2, kBox): run_2d<Real, 2, kBox>(J, pass, t, hq, lane); break;
+          case batch_variant(2, 2, kGeneral): run_2d<Real, 2, kGeneral>(J, pass, t, hq, lane); break;
+          case batch_variant(2, 3, kStar): run_2d<Real, 3, kStar>(J, pass, t, hq, lane); break;
+          case batch_variant(2, 3, kBox): run_2d<Real, 3, kBox>(J, pass, t, hq, lane); break;
+          case batch_variant(2, 4, kStar): run_2d<Real, 4, kStar>(J, pass, t, hq, lane); break;
+          case batch_variant(2, 4, kBox): run_2d<Real, 4, kBox>(J, pass, t, hq, lane); break;
+          default: break;
+        }
+      }
+    } else if (ok) {
+      switch (variant) {
+        case batch_variant(3, 1, kStar): run_3d<Real, 1, kStar>(J, pass, sub, lds_raw); break;
+        case batch_variant(3, 1, kBox): run_3d<Real, 1, kBox>(J, pass, sub, lds_raw); break;
+        case batch_variant(3, 1, kGeneral): run_3d<Real, 1, kGeneral>(J, pass, sub, lds_raw); break;
+        case batch_variant(3, 2, kStar): run_3d<Real, 2, kStar>(J, pass, sub, lds_raw); break;
+        default: break;
+      }
     }
     // every wave's stores are released before the count is published
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (wave0)
-      __hip_atomic_fetch_add(q.done + job, lane == 0 ? 1u : 0u, __ATOMIC_RELEASE,
+      __hip_atomic_fetch_add(q.done + job, lane == 0 ? ndone : 0u, __ATOMIC_RELEASE,
                              __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -213,52 +240,13 @@ __global__ __launch_bounds__(tb3d::kThreads) void tb3d_batch_kernel(const Batch3
 namespace stencil_impl {
 namespace batch {
 
-template <typename Real, int R, int SHAPE>
-hipError_t launch2d(const Batch2DParams<Real>* p, int grid, size_t lds, hipStream_t s) {
-  constexpr int D = max_depth_c(R, SHAPE);
-  if constexpr (D == 0) {
-    return hipErrorInvalidValue;
-  } else {
-    const void* fn = (const void*)&tb2d_batch_kernel<Real, R, SHAPE, D>;
-    void* args[] = {(void*)p};
-    return hipLaunchKernel(fn, dim3(grid), dim3(256), args, lds, s);
-  }
-}
-
-template <typename Real, int R, int SHAPE>
-hipError_t launch3d(const Batch3DParams<Real>* p, int grid, hipStream_t s) {
-  constexpr int D = tb3d::max_depth_c(sizeof(Real) == 8 ? kF64 : kF32, R, SHAPE);
-  if constexpr (D == 0) {
-    return hipErrorInvalidValue;
-  } else {
-    const void* fn = (const void*)&tb3d_batch_kernel<Real, R, SHAPE, D>;
-    const size_t lds = tb3d::Lds<Real, R>::kBytes;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    void* args[] = {(void*)p};
-    return hipLaunchKernel(fn, dim3(grid), dim3(tb3d::kThreads), args, lds, s);
-  }
-}
-
-template <typename Real, int R>
-hipError_t launch2d_shape(int shape, const Batch2DParams<Real>* p, int grid, size_t lds,
-                          hipStream_t s) {
-  switch (shape) {
-    case kStar: return launch2d<Real, R, kStar>(p, grid, lds, s);
-    case kBox: return launch2d<Real, R, kBox>(p, grid, lds, s);
-    case kGeneral: return launch2d<Real, R, kGeneral>(p, grid, lds, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <typename Real, int R>
-hipError_t launch3d_shape(int shape, const Batch3DParams<Real>* p, int grid, hipStream_t s) {
-  switch (shape) {
-    case kStar: return launch3d<Real, R, kStar>(p, grid, s);
-    case kBox: return launch3d<Real, R, kBox>(p, grid, s);
-    case kGeneral: return launch3d<Real, R, kGeneral>(p, grid, s);
-    default: return hipErrorInvalidValue;
-  }
+template <typename Real>
+hipError_t launch(const BatchParams<Real>* p, int grid, size_t lds, hipStream_t s) {
+  const void* fn = (const void*)&batch_kernel<Real>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {(void*)p};
+  return hipLaunchKernel(fn, dim3(grid), dim3(256), args, lds, s);
 }
 
 }  // namespace batch

@@ -46,12 +46,13 @@ struct Tb3dParams {
 };
 
 // ---- batched persistent execution ----------------------------------------
-// A batch runs many independent grids in persistent launches (one per kernel
-// variant). Work items are (job, pass, tile); they are listed as chunks (job,
-// pass) in an order where every pass of a job follows its previous pass, and
-// the item counter walks them. A tile of pass p of job j starts once all
-// tiles of pass p-1 of job j are done (done[j] >= p * tiles), which also
-// covers the reuse of the ping-pong buffers.
+// A batch runs many independent grids in one persistent launch per dtype.
+// Work items are a workgroup's share of one (job, pass): a 3D tile, or up to
+// four 2D wave tiles. Items are listed as chunks (job, pass) in an order where
+// every pass of a job follows its previous pass, and the item counter walks
+// them. Tiles of pass p of job j start once all tiles of pass p-1 of job j are
+// done (done[j] >= p * tiles), which also covers the reuse of the ping-pong
+// buffers.
 struct BatchQueue {
   const int32_t* chunk_job;
   const int32_t* chunk_pass;
@@ -64,37 +65,30 @@ struct BatchQueue {
   int64_t timeout_ticks;       // s_memrealtime ticks (100 MHz)
 };
 
-template <typename Real>
-struct BatchJob2D {
-  const void* in;
-  void* out;
-  void* ws;
-  int64_t P, Q;
-  int32_t strips, segs, seg_len, tiles, hl, npass, depth, depth_last;
-  Real w[kMaxBox2D];
-};
+// Variant index of a batched job: 2D variants 0..11, 3D variants 12..23.
+constexpr int kBatch3DBase = 12;
+constexpr int batch_variant(int ndim, int r, int shape) {
+  return (ndim - 2) * kBatch3DBase + (r - 1) * 3 + shape;
+}
 
+// One batched grid. 2D: P = padded x extent, Qy = padded y extent, strips x
+// segments tiles of one wave. 3D: P, Qy, Qz padded extents, sx x sy x
+// segments tiles of one workgroup.
 template <typename Real>
-struct BatchJob3D {
+struct BatchJob {
   const void* in;
   void* out;
   void* ws;
   int64_t P, Qy, Qz;
-  int32_t sx, sy, segs, seg_len, tiles, hx, hy, npass, depth, depth_last;
+  int32_t variant, tiles, strips, seg_len, hl, sx, sy, hx, hy, npass, depth, depth_last;
   Real w[125];
 };
 
 template <typename Real>
-struct Batch2DParams {
-  const BatchJob2D<Real>* jobs;
+struct BatchParams {
+  const BatchJob<Real>* jobs;
   BatchQueue q;
-  int32_t hq_rows;  // LDS halo rows per wave (maximum over the jobs)
-};
-
-template <typename Real>
-struct Batch3DParams {
-  const BatchJob3D<Real>* jobs;
-  BatchQueue q;
+  int32_t hq_stride;  // LDS halo-queue elements per wave (2D tiles)
 };
 
 // Halo-frame copies for many grids in one launch.
@@ -105,10 +99,12 @@ struct FrameCopyJob {
   int32_t r[3];
 };
 
-hipError_t tb2d_batch_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
-                             size_t lds_bytes, hipStream_t stream);
-hipError_t tb3d_batch_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
-                             hipStream_t stream);
+// The fused persistent batch kernel of a dtype (grid workgroups of 256).
+hipError_t batch_launch(int dtype, const void* params, int grid, size_t lds_bytes, hipStream_t stream);
+// Deepest compiled depth of a batched variant (0: none), and the LDS bytes a
+// 3D variant needs.
+int batch_max_depth(int dtype, int ndim, int r, int shape);
+size_t batch_lds_3d(int dtype, int r);
 hipError_t frame_copy_batch_launch(int dtype, const FrameCopyJob* jobs_dev, int njobs,
                                    hipStream_t stream);
 

@@ -1,0 +1,412 @@
+// Serving loop: requests arrive at any time, are admitted by device-memory
+// budget and slots, stay resident on the device, and advance in rounds. Each
+// round runs one quantum of every resident request in one batched persistent
+// launch (stencil_batch_submit), so requests that arrive while others run are
+// batched with them from the next round on (continuous batching). A quantum is
+// a few passes of the request's temporal depth; running T steps as several
+// quanta is the same arithmetic as one run, so results do not depend on the
+// mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "plan.hpp"
+
+using namespace stencil_impl;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+enum class RState { kQueued, kResident, kDone, kFailed };
+
+struct Request {
+  uint64_t ticket = 0;
+  std::vector<double> coeffs;
+  stencil_job job;  // in/out unused; coeffs points into `coeffs`
+  std::vector<char> host_in;
+  size_t bytes = 0;  // one padded grid
+  size_t need = 0;   // device bytes held while resident
+  int64_t remaining = 0;
+  int64_t quantum = 1;  // steps per round
+  char* dev = nullptr;  // two padded grids
+  int cur = 0;          // which half holds the current state
+  RState state = RState::kQueued;
+  bool collecting = false;
+  stencil_status err = STENCIL_OK;
+  Clock::time_point t_submit, t_done;
+  double updates = 0;
+  void* grid(int k) const { return dev + (size_t)k * ((bytes + 255) / 256 * 256); }
+};
+
+}  // namespace
+
+struct stencil_server_s {
+  stencil_server_config cfg;
+  hipStream_t compute = nullptr, copy = nullptr, collect = nullptr;
+  hipEvent_t round_end = nullptr, inputs_ready = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_work;  // new submissions or stop
+  std::condition_variable cv_done;  // a request finished
+  std::deque<Request*> queue;
+  std::vector<Request*> resident;  // admitted, not yet collected
+  std::map<uint64_t, std::unique_ptr<Request>> all;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  bool pending_inputs = false;  // copies enqueued since the last round started
+  std::thread worker;
+  // statistics
+  stencil_server_statistics st;
+  std::vector<double> latencies;
+  bool any_submit = false;
+  Clock::time_point first_submit, last_done;
+  std::mutex collect_mu;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+void finish_locked(stencil_server_s* srv, Request* r, RState s, stencil_status err) {
+  r->state = s;
+  r->err = err;
+  r->t_done = Clock::now();
+  if (s == RState::kDone) {
+    const double lat = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    srv->latencies.push_back(lat);
+    srv->st.completed++;
+    srv->st.cell_updates += r->updates;
+    srv->last_done = r->t_done;
+  } else {
+    srv->st.failed++;
+  }
+}
+
+// Admit queued requests in arrival order while a slot and the budget allow;
+// their inputs are copied on the copy stream. Called with srv->mu held.
+void admit_locked(stencil_server_s* srv) {
+  while (!srv->queue.empty()) {
+    Request* r = srv->queue.front();
+    if ((int)srv->resident.size() >= srv->cfg.max_slots) break;
+    if (srv->st.hbm_in_use + r->need > srv->cfg.hbm_budget_bytes) break;
+    srv->queue.pop_front();
+    const size_t two = 2 * align256(r->bytes);
+    hipError_t e = hipMallocAsync((void**)&r->dev, two, srv->copy);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(r->dev, r->host_in.data(), r->bytes, hipMemcpyHostToDevice, srv->copy);
+    if (e != hipSuccess) {
+      if (r->dev) (void)hipFreeAsync(r->dev, srv->copy);
+      r->dev = nullptr;
+      r->state = RState::kFailed;
+      r->err = STENCIL_ERR_NOMEM;
+      r->t_done = Clock::now();
+      srv->st.failed++;
+      srv->cv_done.notify_all();
+      continue;
+    }
+    srv->st.hbm_in_use += r->need;
+    srv->st.hbm_peak = std::max(srv->st.hbm_peak, srv->st.hbm_in_use);
+    srv->st.admitted++;
+    srv->resident.push_back(r);
+    srv->pending_inputs = true;
+    r->state = RState::kResident;
+    if (r->remaining == 0) finish_locked(srv, r, RState::kDone, STENCIL_OK);  // T = 0: input is the result
+  }
+  int active = 0;
+  for (Request* r : srv->resident) active += r->state == RState::kResident;
+  srv->st.active = active;
+  srv->st.max_active = std::max(srv->st.max_active, active);
+  srv->st.queued = (int32_t)srv->queue.size();
+}
+
+void scheduler(stencil_server_s* srv) {
+  (void)hipSetDevice(srv->cfg.device);
+  std::unique_lock<std::mutex> lock(srv->mu);
+  while (true) {
+    if (srv->stop) break;
+    admit_locked(srv);
+    std::vector<Request*> round;
+    for (Request* r : srv->resident)
+      if (r->state == RState::kResident) round.push_back(r);
+    if (round.empty()) {
+      if (srv->stop) break;
+      srv->cv_done.notify_all();  // T = 0 requests admitted just now
+      srv->cv_work.wait(lock, [&] { return srv->stop || !srv->queue.empty(); });
+      if (srv->stop) break;
+      continue;
+    }
+    // one quantum of every resident request, in one batched launch
+    std::vector<stencil_job> jobs(round.size());
+    std::vector<int64_t> steps(round.size());
+    for (size_t k = 0; k < round.size(); ++k) {
+      Request* r = round[k];
+      steps[k] = std::min(r->remaining, r->quantum);
+      jobs[k] = r->job;
+      jobs[k].T = steps[k];
+      jobs[k].in = r->grid(r->cur);
+      jobs[k].out = r->grid(1 - r->cur);
+      jobs[k].tag = r->ticket;
+    }
+    const bool wait_inputs = srv->pending_inputs;
+    srv->pending_inputs = false;
+    lock.unlock();
+    stencil_status st = STENCIL_OK;
+    if (wait_inputs) {
+      if (hipEventRecord(srv->inputs_ready, srv->copy) != hipSuccess ||
+          hipStreamWaitEvent(srv->compute, srv->inputs_ready, 0) != hipSuccess)
+        st = hip_fail(hipErrorUnknown, "server input ordering");
+    }
+    std::vector<stencil_status> js(round.size(), STENCIL_OK);
+    const Clock::time_point t0 = Clock::now();
+    if (st == STENCIL_OK)
+      st = stencil_batch_submit(jobs.data(), (int32_t)jobs.size(), srv->compute, js.data());
+    if (st == STENCIL_OK && hipEventRecord(srv->round_end, srv->compute) != hipSuccess)
+      st = hip_fail(hipErrorUnknown, "server round event");
+    // while the round runs, admit arrivals so their inputs are on the device
+    // by the next round
+    lock.lock();
+    while (st == STENCIL_OK) {
+      const hipError_t q = hipEventQuery(srv->round_end);
+      if (q == hipSuccess) break;
+      if (q != hipErrorNotReady) {
+        st = hip_fail(q, "server round");
+        break;
+      }
+      admit_locked(srv);
+      srv->cv_work.wait_for(lock, std::chrono::microseconds(100));
+    }
+    lock.unlock();
+    if (st == STENCIL_OK) st = stencil_sync(srv->compute);
+    const double busy = std::chrono::duration<double>(Clock::now() - t0).count();
+    lock.lock();
+    srv->st.rounds++;
+    srv->st.busy_s += busy;
+    for (size_t k = 0; k < round.size(); ++k) {
+      Request* r = round[k];
+      if (st != STENCIL_OK || js[k] != STENCIL_OK) {
+        finish_locked(srv, r, RState::kFailed, st != STENCIL_OK ? st : js[k]);
+        continue;
+      }
+      r->cur = 1 - r->cur;
+      r->remaining -= steps[k];
+      if (r->remaining == 0) finish_locked(srv, r, RState::kDone, STENCIL_OK);
+    }
+    srv->cv_done.notify_all();
+  }
+}
+
+// Give back a collected (or dropped) request's device memory. mu held.
+void release_locked(stencil_server_s* srv, Request* r) {
+  auto it = std::find(srv->resident.begin(), srv->resident.end(), r);
+  if (it != srv->resident.end()) {
+    srv->resident.erase(it);
+    srv->st.hbm_in_use -= r->need;
+  }
+  if (r->dev) (void)hipFreeAsync(r->dev, srv->collect);
+  r->dev = nullptr;
+  srv->cv_work.notify_all();  // a slot and memory are free again
+}
+
+stencil_status collect(stencil_server_s* srv, uint64_t ticket, void* host_out, bool block,
+                       int32_t* done, double* latency_s) {
+  std::unique_lock<std::mutex> lock(srv->mu);
+  auto it = srv->all.find(ticket);
+  if (it == srv->all.end()) return fail(STENCIL_ERR_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+  Request* r = it->second.get();
+  if (block)
+    srv->cv_done.wait(lock, [&] { return r->state == RState::kDone || r->state == RState::kFailed; });
+  if (r->state != RState::kDone && r->state != RState::kFailed) {
+    if (done) *done = 0;
+    return STENCIL_OK;
+  }
+  if (r->collecting) return fail(STENCIL_ERR_INVALID, "ticket %llu is being collected", (unsigned long long)ticket);
+  if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  stencil_status st = r->err;
+  if (st == STENCIL_OK && host_out) {
+    // the round that finished the request is complete; copy on the collect
+    // stream without holding the scheduler's lock
+    r->collecting = true;
+    const void* src = r->grid(r->cur);
+    const size_t bytes = r->bytes;
+    lock.unlock();
+    hipError_t e;
+    {
+      std::lock_guard<std::mutex> cl(srv->collect_mu);
+      e = hipMemcpyAsync(host_out, src, bytes, hipMemcpyDeviceToHost, srv->collect);
+      if (e == hipSuccess) e = hipStreamSynchronize(srv->collect);
+    }
+    lock.lock();
+    if (e != hipSuccess) st = hip_fail(e, "server result copy");
+  }
+  release_locked(srv, r);
+  srv->all.erase(it);
+  if (done) *done = 1;
+  return st == STENCIL_OK ? STENCIL_OK : fail(st, "request %llu failed", (unsigned long long)ticket);
+}
+
+}  // namespace
+
+extern "C" {
+
+stencil_status stencil_server_create(const stencil_server_config* config, stencil_server_t* server) {
+  if (!config || !server) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  *server = nullptr;
+  if (config->max_slots < 1) return fail(STENCIL_ERR_INVALID, "max_slots must be >= 1");
+  if (config->hbm_budget_bytes == 0) return fail(STENCIL_ERR_INVALID, "HBM budget must be > 0");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || config->device < 0 || config->device >= ndev)
+    return fail(STENCIL_ERR_DEVICE, "HIP device %d is not available", config->device);
+  std::unique_ptr<stencil_server_s> srv(new (std::nothrow) stencil_server_s());
+  if (!srv) return fail(STENCIL_ERR_NOMEM, "host allocation failed");
+  srv->cfg = *config;
+  if (srv->cfg.quantum_passes <= 0) srv->cfg.quantum_passes = 4;
+  std::memset(&srv->st, 0, sizeof(srv->st));
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  hipError_t e = hipSetDevice(config->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->compute, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->copy, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->collect, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->round_end, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->inputs_ready, hipEventDisableTiming);
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) {
+    stencil_server_destroy(srv.release());
+    return hip_fail(e, "server streams");
+  }
+  stencil_server_s* raw = srv.release();
+  raw->worker = std::thread(scheduler, raw);
+  *server = raw;
+  return STENCIL_OK;
+}
+
+stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* job, const void* host_in,
+                                     uint64_t* ticket) {
+  if (!srv || !job || !host_in || !ticket) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  stencil_plan_t pl = nullptr;
+  stencil_status st = stencil_plan(&pl, job->coeffs, job->radius, &job->shape, job->dtype, job->T, nullptr);
+  if (st != STENCIL_OK) {
+    std::lock_guard<std::mutex> lock(srv->mu);
+    srv->st.rejected++;
+    return st;
+  }
+  std::unique_ptr<Request> r(new (std::nothrow) Request());
+  if (!r) {
+    stencil_plan_destroy(pl);
+    return fail(STENCIL_ERR_NOMEM, "host allocation failed");
+  }
+  r->bytes = (size_t)pl->padded_elems * pl->elem;
+  // two resident grids plus the batch workspace of a round
+  r->need = 2 * align256(r->bytes) + align256(r->bytes);
+  r->remaining = job->T;
+  r->updates = (double)pl->cells * (double)job->T;
+  const int dt = pl->dtype == STENCIL_F64 ? kF64 : kF32;
+  int depth = pl->depth;
+  if (pl->scheme == STENCIL_SCHEME_BLOCKED_2D || pl->scheme == STENCIL_SCHEME_BLOCKED_3D)
+    depth = std::max(1, std::min(depth, batch_max_depth(dt, pl->ndim, pl->r, pl->pattern)));
+  else
+    depth = 1;
+  r->quantum = (int64_t)srv->cfg.quantum_passes * std::max(1, depth);
+  r->coeffs = pl->coeffs;
+  stencil_plan_destroy(pl);
+  if (r->need > srv->cfg.hbm_budget_bytes) {
+    std::lock_guard<std::mutex> lock(srv->mu);
+    srv->st.rejected++;
+    return fail(STENCIL_ERR_BUDGET, "request needs %zu bytes of device memory; the budget is %llu",
+                r->need, (unsigned long long)srv->cfg.hbm_budget_bytes);
+  }
+  r->job = *job;
+  r->job.coeffs = r->coeffs.data();
+  r->job.in = nullptr;
+  r->job.out = nullptr;
+  r->job.depth = 0;
+  r->host_in.resize(r->bytes);
+  std::memcpy(r->host_in.data(), host_in, r->bytes);
+  std::lock_guard<std::mutex> lock(srv->mu);
+  r->ticket = srv->next_ticket++;
+  r->t_submit = Clock::now();
+  if (!srv->any_submit) {
+    srv->any_submit = true;
+    srv->first_submit = r->t_submit;
+  }
+  *ticket = r->ticket;
+  srv->queue.push_back(r.get());
+  srv->all[r->ticket] = std::move(r);
+  srv->st.submitted++;
+  srv->st.queued = (int32_t)srv->queue.size();
+  srv->cv_work.notify_all();
+  return STENCIL_OK;
+}
+
+stencil_status stencil_server_poll(stencil_server_t srv, uint64_t ticket, void* host_out, int32_t* done,
+                                   double* latency_s) {
+  if (!srv || !done) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  return collect(srv, ticket, host_out, false, done, latency_s);
+}
+
+stencil_status stencil_server_wait(stencil_server_t srv, uint64_t ticket, void* host_out, double* latency_s) {
+  if (!srv) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  int32_t done = 0;
+  return collect(srv, ticket, host_out, true, &done, latency_s);
+}
+
+stencil_status stencil_server_stats(stencil_server_t srv, stencil_server_statistics* out) {
+  if (!srv || !out) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lock(srv->mu);
+  *out = srv->st;
+  std::vector<double> l = srv->latencies;
+  std::sort(l.begin(), l.end());
+  auto rank = [&](double p) {
+    const size_t k = (size_t)std::ceil(p * (double)l.size());
+    return l[std::min(l.size() - 1, k == 0 ? 0 : k - 1)];
+  };
+  if (!l.empty()) {
+    out->p50_s = rank(0.50);
+    out->p99_s = rank(0.99);
+    out->max_s = l.back();
+    double sum = 0;
+    for (double v : l) sum += v;
+    out->mean_s = sum / (double)l.size();
+    out->wall_s = std::chrono::duration<double>(srv->last_done - srv->first_submit).count();
+  }
+  return STENCIL_OK;
+}
+
+stencil_status stencil_server_destroy(stencil_server_t srv) {
+  if (!srv) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  {
+    std::lock_guard<std::mutex> lock(srv->mu);
+    srv->stop = true;
+    srv->queue.clear();
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(srv->cfg.device);
+  if (srv->compute) (void)hipStreamSynchronize(srv->compute);
+  if (srv->copy) (void)hipStreamSynchronize(srv->copy);
+  for (auto& kv : srv->all)
+    if (kv.second->dev) (void)hipFreeAsync(kv.second->dev, srv->collect);
+  if (srv->collect) (void)hipStreamSynchronize(srv->collect);
+  if (srv->round_end) (void)hipEventDestroy(srv->round_end);
+  if (srv->inputs_ready) (void)hipEventDestroy(srv->inputs_ready);
+  if (srv->compute) (void)hipStreamDestroy(srv->compute);
+  if (srv->copy) (void)hipStreamDestroy(srv->copy);
+  if (srv->collect) (void)hipStreamDestroy(srv->collect);
+  (void)hipSetDevice(prev);
+  delete srv;
+  return STENCIL_OK;
+}
+
+}  // extern "C"

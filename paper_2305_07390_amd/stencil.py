@@ -111,6 +111,22 @@ class stencil_tune_result(ctypes.Structure):
                 ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
 
 
+class stencil_server_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+                ("quantum_passes", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
+
+
+class stencil_server_statistics(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("active", ctypes.c_int32), ("queued", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("hbm_in_use", ctypes.c_uint64), ("hbm_peak", ctypes.c_uint64),
+                ("cell_updates", ctypes.c_double), ("busy_s", ctypes.c_double), ("wall_s", ctypes.c_double),
+                ("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double), ("mean_s", ctypes.c_double),
+                ("max_s", ctypes.c_double)]
+
+
 MODEL_NO_TILING, MODEL_SM_TILING, MODEL_DEVICE_TILING = 0, 1, 2
 
 _P = ctypes.c_void_p
@@ -143,6 +159,14 @@ _SIGNATURES = {
     "stencil_tune_cache_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
     "stencil_tune_cache_save": (ctypes.c_int, [ctypes.c_char_p]),
     "stencil_tune_cache_clear": (ctypes.c_int, []),
+    "stencil_server_create": (ctypes.c_int, [ctypes.POINTER(stencil_server_config), ctypes.POINTER(_P)]),
+    "stencil_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(stencil_job), _P,
+                                              ctypes.POINTER(ctypes.c_uint64)]),
+    "stencil_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _P, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_double)]),
+    "stencil_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, _P, ctypes.POINTER(ctypes.c_double)]),
+    "stencil_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(stencil_server_statistics)]),
+    "stencil_server_destroy": (ctypes.c_int, [_P]),
     "stencil_last_error": (ctypes.c_char_p, []),
 }
 
@@ -317,6 +341,65 @@ def use_tuned_defaults(path: str = TUNE_CACHE_PATH) -> int:
     if not os.path.exists(path):
         return 0
     return stencil_tune_cache_load(path)
+
+
+def stencil_server_create(hbm_budget_bytes: int, max_slots: int, quantum_passes: int = 0,
+                          device: int = 0):
+    cfg = stencil_server_config()
+    cfg.device = int(device)
+    cfg.max_slots = int(max_slots)
+    cfg.quantum_passes = int(quantum_passes)
+    cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+    h = _P()
+    _check(load_library().stencil_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def _job_struct(coeffs, radius, interior, dtype, T):
+    c, cp = _coeff_ptr(coeffs)
+    j = stencil_job()
+    j.coeffs = cp
+    j.radius = int(radius)
+    j.shape = _shape(interior)
+    j.dtype = _dtype_code(dtype)
+    j.T = int(T)
+    return j, c
+
+
+def stencil_server_submit(server, coeffs, radius: int, interior, T: int, host_in: np.ndarray) -> int:
+    """Submit one request; `host_in` is the padded input (its dtype is the
+    request's). Returns the ticket."""
+    a = np.ascontiguousarray(host_in)
+    j, keep = _job_struct(coeffs, radius, interior, a.dtype, T)
+    t = ctypes.c_uint64()
+    _check(load_library().stencil_server_submit(server, ctypes.byref(j), a.ctypes.data, ctypes.byref(t)))
+    return t.value
+
+
+def stencil_server_poll(server, ticket: int, host_out: np.ndarray | None = None):
+    """(done, latency_s); when done the result is in host_out and the ticket is retired."""
+    done = ctypes.c_int32()
+    lat = ctypes.c_double()
+    ptr = host_out.ctypes.data if host_out is not None else None
+    _check(load_library().stencil_server_poll(server, int(ticket), ptr, ctypes.byref(done), ctypes.byref(lat)))
+    return bool(done.value), lat.value
+
+
+def stencil_server_wait(server, ticket: int, host_out: np.ndarray | None = None) -> float:
+    lat = ctypes.c_double()
+    ptr = host_out.ctypes.data if host_out is not None else None
+    _check(load_library().stencil_server_wait(server, int(ticket), ptr, ctypes.byref(lat)))
+    return lat.value
+
+
+def stencil_server_stats(server) -> dict:
+    s = stencil_server_statistics()
+    _check(load_library().stencil_server_stats(server, ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in s._fields_}
+
+
+def stencil_server_destroy(server):
+    _check(load_library().stencil_server_destroy(server))
 
 
 def run_batch(problems, xs, ys, stream=None, depth=0):
