@@ -7,11 +7,17 @@ coefficients U[0,1) normalised to sum 1, inputs U[0,1) (seeded, synthetic).
 Inputs are resident in HBM before timing starts.
 
 Prints one JSON line: GCells/s over the whole step (cell-updates per second),
-the roofline record of the dominant kernel, the per-stencil breakdown with the
-fraction of the temporally blocked roofline min(t_eff * B / 2S, F / 2k), and
-the CPU oracle timed on a bounded sample of the same workload.
+the roofline record of the dominant kernel (HBM or VALU, whichever bounds it),
+the per-stencil breakdown with the fraction of the temporally blocked roofline
+min(t_eff * B / 2S, F / 2k), and the CPU oracle timed on a bounded sample of
+the same workload. Unless --no-extras is given, the same line also reports the
+other workloads once each: the 3D single-grid suite (512^3, T=200, FP64), the
+heterogeneous batch of 128 grids in one persistent launch per dtype (FP64 and
+FP32, with the FP32 error against the FP64 result) and a short run of the
+serving loop under Poisson arrivals (FP32, p50/p99 latency).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--T 1000]
+                       [--no-cpu] [--no-extras] [--serve-seconds S]
 """
 from __future__ import annotations
 
@@ -150,6 +156,107 @@ def probe():
         torch.cuda.empty_cache()
 
 
+def timed(torch, fn):
+    """Run fn once on the current stream between two events; seconds."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3
+
+
+def bench_3d(torch, np, stencil, workloads, n=512, T=200):
+    """3D single-grid suite, FP64: one timed run per stencil after a warm-up."""
+    rows, total_t, total_u = [], 0.0, 0
+    for prob in workloads.suite_3d_problems(n, T):
+        x = torch.from_numpy(prob.field(np.float64)).cuda()
+        y = torch.empty_like(x)
+        plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, prob.T)
+        plan.execute(x, y)
+        t = timed(torch, lambda: plan.execute(x, y))
+        rows.append({"stencil": prob.spec.name, "scheme": plan.info["scheme_name"],
+                     "depth": plan.info["depth"], "ms": round(t * 1e3, 2),
+                     "gcells_per_s": round(prob.updates / t / 1e9, 1)})
+        total_t += t
+        total_u += prob.updates
+        log(f"  3d {rows[-1]}")
+        plan.close()
+        del x, y
+        torch.cuda.empty_cache()
+    return {"workload": f"3D single-grid suite {n}^3 FP64, T={T}", "gcells_per_s":
+            round(total_u / total_t / 1e9, 1), "per_stencil": rows}
+
+
+def bench_batch(torch, np, stencil, workloads):
+    """128 heterogeneous grids, one batched submission per dtype."""
+    probs = workloads.batch_problems()
+    upd = sum(p.updates for p in probs)
+    out = {"workload": "128 grids: 2D sides log-U[512,4096], 3D log-U[64,256], T~U{50..500}, "
+                       "7 stencil types", "grids": len(probs), "cell_updates": upd}
+    ys_by = {}
+    for dt, name in ((np.float64, "f64"), (np.float32, "f32")):
+        xs = [torch.from_numpy(p.field(np.float64).astype(dt)).cuda() for p in probs]
+        ys = [torch.empty_like(x) for x in xs]
+        stencil.run_batch(probs, xs, ys)
+        stencil.stencil_sync()
+        t = timed(torch, lambda: stencil.run_batch(probs, xs, ys))
+        stencil.stencil_sync()
+        out[name] = {"s": round(t, 4), "gcells_per_s": round(upd / t / 1e9, 1)}
+        log(f"  batch {name}: {out[name]}")
+        ys_by[name] = ys
+        del xs
+    err = 0.0
+    for a, b in zip(ys_by["f64"], ys_by["f32"]):
+        scale = float(a.abs().max())
+        err = max(err, float((b.double() - a).abs().max()) / max(scale, 1e-300))
+    out["f32_max_err_rel_to_max"] = err
+    del ys_by
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(np, torch, stencil, workloads, seconds=3.0, rate=200.0):
+    """Serving loop under open-loop Poisson arrivals, FP32, 200 GB budget."""
+    from paper_2305_07390_amd import serving
+    count = max(1, int(seconds * rate))
+    reqs, arr = workloads.serving_requests(count, rate_hz=rate, dtype=np.float32)
+    offered = sum(p.cells * T for p, _, T in reqs) / max(float(arr[-1]), 1e-9)
+    # FP32 error against the FP64 path for the first few requests
+    sample = {}
+    def keep(k, res):
+        if k < 8:
+            sample[k] = res
+    with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=64, quantum_passes=4) as srv:
+        res = serving.serve_open_loop(srv, reqs, arr, on_result=keep)
+    s = res["stats"]
+    err = 0.0
+    for k, got in sample.items():
+        prob, field, T = reqs[k]
+        x = torch.from_numpy(field.astype(np.float64)).cuda()
+        y = torch.empty_like(x)
+        plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, T)
+        plan.execute(x, y)
+        torch.cuda.synchronize()
+        ref = y.cpu().numpy()
+        plan.close()
+        err = max(err, float(np.max(np.abs(got.astype(np.float64) - ref))) / float(np.max(np.abs(ref))))
+    out = {"workload": f"Poisson arrivals {rate:g} req/s for {seconds:g} s, grids drawn like the "
+                       "batch (pool of 32), FP32, 200 GB HBM budget",
+           "requests": count, "completed": s["completed"], "rejected": len(res["rejected"]),
+           "offered_gcells_per_s": round(offered / 1e9, 1),
+           "throughput_gcells_per_s": round(s["cell_updates"] / max(s["wall_s"], 1e-9) / 1e9, 1),
+           "p50_ms": round(s["p50_s"] * 1e3, 2), "p99_ms": round(s["p99_s"] * 1e3, 2),
+           "mean_ms": round(s["mean_s"] * 1e3, 2), "rounds": s["rounds"],
+           "max_active": s["max_active"], "hbm_peak_GB": round(s["hbm_peak"] / 1e9, 2),
+           "device_busy_frac": round(s["busy_s"] / max(s["wall_s"], 1e-9), 3),
+           "submit_lag_ms": round(res["submit_lag_s"] * 1e3, 2),
+           "f32_max_err_rel_to_max_sample8": err}
+    log(f"  serving: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +265,9 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--T", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 3D suite, batch and serving measurements")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--depth", type=int, default=0, help="force a temporal depth (0 = plan)")
     ap.add_argument("--probe", action="store_true",
                     help="run the short program used for PMC counter passes and exit")
@@ -256,9 +366,24 @@ def main():
             dominant = (t, row, bytes_per_launch, per_launch)
 
     _, drow, dbytes, dlaunch = dominant
-    achieved = dbytes / dlaunch / 1e9
+    dprob = problems[[r["stencil"] for r in breakdown].index(drow["stencil"])]
     dtag = f"tb2d<double,{drow['radius']},{drow['pattern_code']},{drow['depth']}>"
     traffic = measured_traffic(dtag)
+    # the bound of the dominant kernel: HBM (one read and one write of every
+    # cell per pass) or VALU (2k flops per cell-update, depth updates per pass)
+    hbm_rate = drow["t_eff"] * HBM_PEAK_GBS / (2 * S)
+    valu_rate = FP64_VALU_TFLOPS * 1e3 / (2 * drow["points"])
+    if hbm_rate <= valu_rate:
+        roof = {"bound": "hbm", "achieved": round(dbytes / dlaunch / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s"}
+    else:
+        flops = 2 * drow["points"] * dprob.cells * drow["depth"]
+        roof = {"bound": "alu", "achieved": round(flops / dlaunch / 1e12, 2), "peak": FP64_VALU_TFLOPS,
+                "unit": "TFLOP/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = traffic
+    roof["kernel"] = f"tb2d ({drow['stencil']}, depth {drow['depth']})"
+    roof["kernel_source"] = kernel_source_hash()
     result = {
         "metric": "GCells/s (cell-updates per second), 2D single-grid suite",
         "value": round(value, 2),
@@ -277,19 +402,19 @@ def main():
                         "5pt star r1 + 9pt box r1 + 13pt star r3 + 25pt box r2, Dirichlet halo",
             "grid": [args.n, args.n], "T": args.T, "stencils": [p.spec.name for p in problems],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": f"tb2d ({drow['stencil']}, depth {drow['depth']})",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel_source": kernel_source_hash(),
-        },
+        "roofline": roof,
         "copy_bandwidth_GBs": round(B, 1),
         "per_stencil": breakdown,
     }
+    del xs, ys
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("3D suite ...")
+        result["suite_3d"] = bench_3d(torch, np, stencil, workloads)
+        log("batch ...")
+        result["batch"] = bench_batch(torch, np, stencil, workloads)
+        log("serving ...")
+        result["serving"] = bench_serving(np, torch, stencil, workloads, seconds=args.serve_seconds)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(problems, fields)

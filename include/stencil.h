@@ -67,7 +67,12 @@ typedef struct {
  * depth: time steps fused per pass over HBM (paper Section 6.2).
  * tile[0]: rows (2D) or planes (3D) per streamed segment; tile[1..2] reserved.
  * flags: STENCIL_FLAG_NAIVE forces one plain step per pass;
- *        STENCIL_FLAG_NO_CACHE ignores the autotuner's cache. */
+ *        STENCIL_FLAG_NO_CACHE ignores the autotuner's cache;
+ *        STENCIL_FLAG_PERSISTENT runs all passes of a blocked plan in one
+ *        persistent launch (one workgroup per CU), each pass starting once the
+ *        grid-wide count of finished tiles of the previous pass is complete (the
+ *        inter-pass grid synchronisation of paper Section 2.1.3, bounded by a
+ *        watchdog that stencil_sync reports); ignored for other schemes. */
 typedef struct {
   int32_t tile[3];
   int32_t depth;
@@ -76,6 +81,7 @@ typedef struct {
 
 #define STENCIL_FLAG_NAIVE 1
 #define STENCIL_FLAG_NO_CACHE 2
+#define STENCIL_FLAG_PERSISTENT 4
 
 /* Execution scheme chosen by a plan. */
 typedef enum {

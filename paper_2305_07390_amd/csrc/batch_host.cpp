@@ -113,6 +113,210 @@ BatchJob<Real> make_job(const stencil_plan_s* p, const void* in, void* out, void
 
 }  // namespace
 
+namespace stencil_impl {
+
+// Runs prepared plans (not owned; NULL entries are skipped) from ins[i] to
+// outs[i] on stream s: blocked plans in one persistent launch per dtype, the
+// others with their plain kernels. wsg[i], when not NULL, is the caller's
+// workspace for plan i; the rest of the workspace and control memory is one
+// stream-ordered allocation released on s.
+stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::vector<const void*>& ins,
+                         const std::vector<void*>& outs, const std::vector<void*>& wsg, hipStream_t s) {
+  const int n = (int)plans.size();
+  // groups of blocked jobs by dtype; everything else runs alone
+  Group groups[2];
+  groups[kF32].dtype = kF32;
+  groups[kF64].dtype = kF64;
+  std::vector<int> alone;
+  for (int i = 0; i < n; ++i) {
+    stencil_plan_s* p = plans[i];
+    if (!p) continue;
+    const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
+    const bool blocked = p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D;
+    if (blocked && p->depth <= batch_max_depth(dt, p->ndim, p->r, p->pattern))
+      groups[dt].jobs.push_back(i);
+    else
+      alone.push_back(i);
+  }
+
+  // device memory: workspaces, then per-group control blocks, then frame-copy lists
+  char* dev = nullptr;
+  std::vector<size_t> ws_off(n, 0);
+  size_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i] || plans[i]->workspace == 0 || wsg[i]) continue;
+    ws_off[i] = total;
+    total = align256(total + plans[i]->workspace);
+  }
+  auto ws_of = [&](int i) -> void* {
+    if (!plans[i]->workspace) return nullptr;
+    return wsg[i] ? wsg[i] : (void*)(dev + ws_off[i]);
+  };
+  struct GroupMem {
+    size_t jobs_off = 0, cj_off = 0, cp_off = 0, cf_off = 0, cursor_off = 0, done_off = 0;
+    std::vector<int32_t> cj, cp;
+    std::vector<int64_t> cf;
+    int64_t hq_stride = 0;  // LDS halo elements per wave (2D jobs)
+    size_t lds = 0;
+  };
+  GroupMem gmem[2];
+  for (int d = 0; d < 2; ++d) {
+    Group& g = groups[d];
+    if (g.jobs.empty()) continue;
+    GroupMem& m = gmem[d];
+    build_worklist(plans, g.jobs, m.cj, m.cp, m.cf);
+    const size_t job_sz = d == kF64 ? sizeof(BatchJob<double>) : sizeof(BatchJob<float>);
+    const size_t elem = d == kF64 ? 8 : 4;
+    m.jobs_off = total;
+    total = align256(total + job_sz * g.jobs.size());
+    m.cj_off = total;
+    total = align256(total + 4 * m.cj.size());
+    m.cp_off = total;
+    total = align256(total + 4 * m.cp.size());
+    m.cf_off = total;
+    total = align256(total + 8 * m.cf.size());
+    m.cursor_off = total;
+    total = align256(total + 8);
+    m.done_off = total;
+    total = align256(total + 4 * g.jobs.size());
+    for (int i : g.jobs) {
+      const stencil_plan_s* p = plans[i];
+      if (p->ndim == 2) m.hq_stride = std::max<int64_t>(m.hq_stride, (int64_t)p->hq_rows * 2 * p->r);
+      else m.lds = std::max(m.lds, batch_lds_3d(d, p->r));
+    }
+    m.lds = std::max(m.lds, (size_t)(4 * m.hq_stride) * elem);
+  }
+  std::vector<FrameCopyJob> frames[2];  // per dtype
+  for (int d = 0; d < 2; ++d)
+    for (int i : groups[d].jobs) {
+      const stencil_plan_s* p = plans[i];
+      FrameCopyJob f;
+      std::memset(&f, 0, sizeof(f));
+      f.src = ins[i];
+      for (int k = 0; k < 3; ++k) {
+        f.ext[k] = p->ext[k];
+        f.r[k] = p->rad[k];
+      }
+      f.dst = outs[i];
+      frames[d].push_back(f);
+      if (p->workspace) {
+        f.dst = nullptr;  // filled once the block address is known
+        frames[d].push_back(f);
+      }
+    }
+  size_t frames_off[2];
+  for (int d = 0; d < 2; ++d) {
+    frames_off[d] = total;
+    total = align256(total + sizeof(FrameCopyJob) * frames[d].size());
+  }
+  for (int d = 0; d < 2; ++d)
+    if (gmem[d].lds > (size_t)160 * 1024) {
+      return fail(STENCIL_ERR_UNSUPPORTED, "batch needs %zu bytes of LDS per workgroup", gmem[d].lds);
+    }
+
+  if (total) {
+    hipError_t e = hipMallocAsync((void**)&dev, total, s);
+    if (e != hipSuccess) {
+      return fail(STENCIL_ERR_NOMEM, "batch allocation of %zu bytes failed: %s", total,
+                  hipGetErrorString(e));
+    }
+  }
+  unsigned int* err = device_error_word();
+  if (!err) {
+    if (dev) hipFreeAsync(dev, s);
+    return fail(STENCIL_ERR_NOMEM, "device error word allocation failed");
+  }
+
+  // host image of the control region (everything after the workspaces is
+  // small); counters start at zero
+  size_t ctl_lo = total;
+  for (int d = 0; d < 2; ++d) {
+    if (!groups[d].jobs.empty()) ctl_lo = std::min(ctl_lo, gmem[d].jobs_off);
+    ctl_lo = std::min(ctl_lo, frames_off[d]);
+  }
+  std::vector<char> img(total - ctl_lo, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(img.data() + (off - ctl_lo), src, bytes);
+  };
+  for (int d = 0; d < 2; ++d) {
+    Group& g = groups[d];
+    GroupMem& m = gmem[d];
+    for (size_t local = 0; local < g.jobs.size(); ++local) {
+      const int i = g.jobs[local];
+      const stencil_plan_s* p = plans[i];
+      void* ws = ws_of(i);
+      if (d == kF64) {
+        const BatchJob<double> J = make_job<double>(p, ins[i], outs[i], ws);
+        put(m.jobs_off + local * sizeof(J), &J, sizeof(J));
+      } else {
+        const BatchJob<float> J = make_job<float>(p, ins[i], outs[i], ws);
+        put(m.jobs_off + local * sizeof(J), &J, sizeof(J));
+      }
+    }
+    if (g.jobs.empty()) continue;
+    put(m.cj_off, m.cj.data(), 4 * m.cj.size());
+    put(m.cp_off, m.cp.data(), 4 * m.cp.size());
+    put(m.cf_off, m.cf.data(), 8 * m.cf.size());
+  }
+  for (int d = 0; d < 2; ++d) {
+    // second entry of a pair targets the job's workspace
+    size_t k = 0;
+    for (int i : groups[d].jobs) {
+      ++k;  // the `out` entry
+      if (plans[i]->workspace) frames[d][k++].dst = ws_of(i);
+    }
+    put(frames_off[d], frames[d].data(), sizeof(FrameCopyJob) * frames[d].size());
+  }
+  hipError_t e = hipSuccess;
+  if (!img.empty()) e = hipMemcpyAsync(dev + ctl_lo, img.data(), img.size(), hipMemcpyHostToDevice, s);
+  stencil_status st = STENCIL_OK;
+  if (e != hipSuccess) st = hip_fail(e, "batch control upload");
+
+  DeviceInfo di = device_info();
+  const int cus = di.ok ? di.cus : 256;
+  for (int d = 0; d < 2 && st == STENCIL_OK; ++d) {
+    e = frame_copy_batch_launch(d, (const FrameCopyJob*)(dev + frames_off[d]), (int)frames[d].size(), s);
+    if (e != hipSuccess) st = hip_fail(e, "batch halo copy");
+  }
+  for (int d = 0; d < 2 && st == STENCIL_OK; ++d) {
+    Group& g = groups[d];
+    if (g.jobs.empty()) continue;
+    GroupMem& m = gmem[d];
+    BatchQueue q;
+    q.chunk_job = (const int32_t*)(dev + m.cj_off);
+    q.chunk_pass = (const int32_t*)(dev + m.cp_off);
+    q.chunk_first = (const int64_t*)(dev + m.cf_off);
+    q.nchunks = (int32_t)m.cj.size();
+    q.nitems = m.cf.back();
+    q.cursor = (unsigned long long*)(dev + m.cursor_off);
+    q.done = (unsigned int*)(dev + m.done_off);
+    q.err = err;
+    q.timeout_ticks = kTimeoutTicks;
+    // one workgroup per CU, never more than there are items
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, q.nitems));
+    if (d == kF64) {
+      BatchParams<double> prm{(const BatchJob<double>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
+      e = batch_launch(d, &prm, grid, m.lds, s);
+    } else {
+      BatchParams<float> prm{(const BatchJob<float>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
+      e = batch_launch(d, &prm, grid, m.lds, s);
+    }
+    if (e != hipSuccess) st = hip_fail(e, "batch launch");
+  }
+  // jobs without a blocked variant: the plain path, workspace from the block
+  for (int i : alone) {
+    if (st != STENCIL_OK) break;
+    st = stencil_execute(plans[i], ins[i], outs[i], ws_of(i), s);
+  }
+  if (dev) {
+    e = hipFreeAsync(dev, s);
+    if (e != hipSuccess && st == STENCIL_OK) st = hip_fail(e, "batch release");
+  }
+  return st;
+}
+
+}  // namespace stencil_impl
+
 extern "C" {
 
 stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* stream,
@@ -199,195 +403,13 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
   for (int i = 0; i < n; ++i) valid += plans[i] != nullptr;
   if (!valid) return fail(STENCIL_ERR_INVALID, "no valid job in the batch");
 
-  // groups of blocked jobs by dtype; everything else runs alone
-  Group groups[2];
-  groups[kF32].dtype = kF32;
-  groups[kF64].dtype = kF64;
-  std::vector<int> alone;
+  std::vector<const void*> ins(n);
+  std::vector<void*> outs(n), wsg(n, nullptr);
   for (int i = 0; i < n; ++i) {
-    stencil_plan_s* p = plans[i];
-    if (!p) continue;
-    const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
-    const bool blocked = p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D;
-    if (blocked && p->depth <= batch_max_depth(dt, p->ndim, p->r, p->pattern))
-      groups[dt].jobs.push_back(i);
-    else
-      alone.push_back(i);
+    ins[i] = jobs[i].in;
+    outs[i] = jobs[i].out;
   }
-
-  // device memory: workspaces, then per-group control blocks, then frame-copy lists
-  std::vector<size_t> ws_off(n, 0);
-  size_t total = 0;
-  for (int i = 0; i < n; ++i) {
-    if (!plans[i] || plans[i]->workspace == 0) continue;
-    ws_off[i] = total;
-    total = align256(total + plans[i]->workspace);
-  }
-  struct GroupMem {
-    size_t jobs_off = 0, cj_off = 0, cp_off = 0, cf_off = 0, cursor_off = 0, done_off = 0;
-    std::vector<int32_t> cj, cp;
-    std::vector<int64_t> cf;
-    int64_t hq_stride = 0;  // LDS halo elements per wave (2D jobs)
-    size_t lds = 0;
-  };
-  GroupMem gmem[2];
-  for (int d = 0; d < 2; ++d) {
-    Group& g = groups[d];
-    if (g.jobs.empty()) continue;
-    GroupMem& m = gmem[d];
-    build_worklist(plans, g.jobs, m.cj, m.cp, m.cf);
-    const size_t job_sz = d == kF64 ? sizeof(BatchJob<double>) : sizeof(BatchJob<float>);
-    const size_t elem = d == kF64 ? 8 : 4;
-    m.jobs_off = total;
-    total = align256(total + job_sz * g.jobs.size());
-    m.cj_off = total;
-    total = align256(total + 4 * m.cj.size());
-    m.cp_off = total;
-    total = align256(total + 4 * m.cp.size());
-    m.cf_off = total;
-    total = align256(total + 8 * m.cf.size());
-    m.cursor_off = total;
-    total = align256(total + 8);
-    m.done_off = total;
-    total = align256(total + 4 * g.jobs.size());
-    for (int i : g.jobs) {
-      const stencil_plan_s* p = plans[i];
-      if (p->ndim == 2) m.hq_stride = std::max<int64_t>(m.hq_stride, (int64_t)p->hq_rows * 2 * p->r);
-      else m.lds = std::max(m.lds, batch_lds_3d(d, p->r));
-    }
-    m.lds = std::max(m.lds, (size_t)(4 * m.hq_stride) * elem);
-  }
-  std::vector<FrameCopyJob> frames[2];  // per dtype
-  for (int d = 0; d < 2; ++d)
-    for (int i : groups[d].jobs) {
-      const stencil_plan_s* p = plans[i];
-      FrameCopyJob f;
-      std::memset(&f, 0, sizeof(f));
-      f.src = jobs[i].in;
-      for (int k = 0; k < 3; ++k) {
-        f.ext[k] = p->ext[k];
-        f.r[k] = p->rad[k];
-      }
-      f.dst = jobs[i].out;
-      frames[d].push_back(f);
-      if (p->workspace) {
-        f.dst = nullptr;  // filled once the block address is known
-        frames[d].push_back(f);
-      }
-    }
-  size_t frames_off[2];
-  for (int d = 0; d < 2; ++d) {
-    frames_off[d] = total;
-    total = align256(total + sizeof(FrameCopyJob) * frames[d].size());
-  }
-  for (int d = 0; d < 2; ++d)
-    if (gmem[d].lds > (size_t)160 * 1024) {
-      for (auto* p : plans) stencil_plan_destroy(p);
-      return fail(STENCIL_ERR_UNSUPPORTED, "batch needs %zu bytes of LDS per workgroup", gmem[d].lds);
-    }
-
-  char* dev = nullptr;
-  if (total) {
-    hipError_t e = hipMallocAsync((void**)&dev, total, s);
-    if (e != hipSuccess) {
-      for (auto* p : plans) stencil_plan_destroy(p);
-      return fail(STENCIL_ERR_NOMEM, "batch allocation of %zu bytes failed: %s", total,
-                  hipGetErrorString(e));
-    }
-  }
-  unsigned int* err = device_error_word();
-  if (!err) {
-    if (dev) hipFreeAsync(dev, s);
-    for (auto* p : plans) stencil_plan_destroy(p);
-    return fail(STENCIL_ERR_NOMEM, "device error word allocation failed");
-  }
-
-  // host image of the control region (everything after the workspaces is
-  // small); counters start at zero
-  size_t ctl_lo = total;
-  for (int d = 0; d < 2; ++d) {
-    if (!groups[d].jobs.empty()) ctl_lo = std::min(ctl_lo, gmem[d].jobs_off);
-    ctl_lo = std::min(ctl_lo, frames_off[d]);
-  }
-  std::vector<char> img(total - ctl_lo, 0);
-  auto put = [&](size_t off, const void* src, size_t bytes) {
-    if (bytes) std::memcpy(img.data() + (off - ctl_lo), src, bytes);
-  };
-  for (int d = 0; d < 2; ++d) {
-    Group& g = groups[d];
-    GroupMem& m = gmem[d];
-    for (size_t local = 0; local < g.jobs.size(); ++local) {
-      const int i = g.jobs[local];
-      const stencil_plan_s* p = plans[i];
-      void* ws = p->workspace ? (void*)(dev + ws_off[i]) : nullptr;
-      if (d == kF64) {
-        const BatchJob<double> J = make_job<double>(p, jobs[i].in, jobs[i].out, ws);
-        put(m.jobs_off + local * sizeof(J), &J, sizeof(J));
-      } else {
-        const BatchJob<float> J = make_job<float>(p, jobs[i].in, jobs[i].out, ws);
-        put(m.jobs_off + local * sizeof(J), &J, sizeof(J));
-      }
-    }
-    if (g.jobs.empty()) continue;
-    put(m.cj_off, m.cj.data(), 4 * m.cj.size());
-    put(m.cp_off, m.cp.data(), 4 * m.cp.size());
-    put(m.cf_off, m.cf.data(), 8 * m.cf.size());
-  }
-  for (int d = 0; d < 2; ++d) {
-    // second entry of a pair targets the job's workspace
-    size_t k = 0;
-    for (int i : groups[d].jobs) {
-      ++k;  // the `out` entry
-      if (plans[i]->workspace) frames[d][k++].dst = dev + ws_off[i];
-    }
-    put(frames_off[d], frames[d].data(), sizeof(FrameCopyJob) * frames[d].size());
-  }
-  hipError_t e = hipSuccess;
-  if (!img.empty()) e = hipMemcpyAsync(dev + ctl_lo, img.data(), img.size(), hipMemcpyHostToDevice, s);
-  stencil_status st = STENCIL_OK;
-  if (e != hipSuccess) st = hip_fail(e, "batch control upload");
-
-  DeviceInfo di = device_info();
-  const int cus = di.ok ? di.cus : 256;
-  for (int d = 0; d < 2 && st == STENCIL_OK; ++d) {
-    e = frame_copy_batch_launch(d, (const FrameCopyJob*)(dev + frames_off[d]), (int)frames[d].size(), s);
-    if (e != hipSuccess) st = hip_fail(e, "batch halo copy");
-  }
-  for (int d = 0; d < 2 && st == STENCIL_OK; ++d) {
-    Group& g = groups[d];
-    if (g.jobs.empty()) continue;
-    GroupMem& m = gmem[d];
-    BatchQueue q;
-    q.chunk_job = (const int32_t*)(dev + m.cj_off);
-    q.chunk_pass = (const int32_t*)(dev + m.cp_off);
-    q.chunk_first = (const int64_t*)(dev + m.cf_off);
-    q.nchunks = (int32_t)m.cj.size();
-    q.nitems = m.cf.back();
-    q.cursor = (unsigned long long*)(dev + m.cursor_off);
-    q.done = (unsigned int*)(dev + m.done_off);
-    q.err = err;
-    q.timeout_ticks = kTimeoutTicks;
-    // one workgroup per CU, never more than there are items
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, q.nitems));
-    if (d == kF64) {
-      BatchParams<double> prm{(const BatchJob<double>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
-      e = batch_launch(d, &prm, grid, m.lds, s);
-    } else {
-      BatchParams<float> prm{(const BatchJob<float>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
-      e = batch_launch(d, &prm, grid, m.lds, s);
-    }
-    if (e != hipSuccess) st = hip_fail(e, "batch launch");
-  }
-  // jobs without a blocked variant: the plain path, workspace from the block
-  for (int i : alone) {
-    if (st != STENCIL_OK) break;
-    void* ws = plans[i]->workspace ? (void*)(dev + ws_off[i]) : nullptr;
-    st = stencil_execute(plans[i], jobs[i].in, jobs[i].out, ws, stream);
-  }
-  if (dev) {
-    e = hipFreeAsync(dev, s);
-    if (e != hipSuccess && st == STENCIL_OK) st = hip_fail(e, "batch release");
-  }
+  stencil_status st = batch_run(plans, ins, outs, wsg, s);
   for (auto* p : plans) stencil_plan_destroy(p);
   return st;
 }

@@ -429,6 +429,22 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
         plan_3d_tiles(p, depth, hint ? hint->tile[0] : 0, cus);
       }
     }
+    const bool want_persistent = hint && (hint->flags & STENCIL_FLAG_PERSISTENT);
+    if (want_persistent &&
+        (p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D)) {
+      // the persistent kernel holds its own (possibly shallower) variants
+      const int cap = batch_max_depth(dtype == STENCIL_F64 ? kF64 : kF32, p->ndim, radius, p->pattern);
+      if (cap >= 1) {
+        p->persistent = true;
+        if (p->depth > cap) {
+          DeviceInfo di = device_info();
+          const int cus = di.ok ? di.cus : 256;
+          p->depth = cap;
+          if (p->scheme == STENCIL_SCHEME_BLOCKED_2D) plan_2d_tiles(p, cap, hint->tile[0], cus);
+          else plan_3d_tiles(p, cap, hint->tile[0], cus);
+        }
+      }
+    }
     if (p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D) {
       int64_t q = T / p->depth, rem = T % p->depth;
       p->pass_depth.assign((size_t)q, p->depth);
@@ -501,6 +517,14 @@ stencil_status stencil_execute(stencil_plan_t plan, const void* in, void* out, v
   if (plan->scheme == STENCIL_SCHEME_COPY) {
     hipError_t e = hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? STENCIL_OK : hip_fail(e, "copy");
+  }
+  if (plan->persistent) {
+    // every pass in one persistent launch, passes separated by the grid-wide
+    // count of finished tiles
+    std::vector<stencil_plan_s*> plans{plan};
+    std::vector<const void*> ins{in};
+    std::vector<void*> outs{out}, wss{workspace};
+    return batch_run(plans, ins, outs, wss, s);
   }
   if (plan->scheme == STENCIL_SCHEME_BLOCKED_2D) {
     return plan->dtype == STENCIL_F64 ? run_blocked_2d<double>(plan, in, out, workspace, s)

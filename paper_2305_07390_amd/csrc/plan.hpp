@@ -27,6 +27,9 @@ struct stencil_plan_s;
 namespace stencil_impl {
 // Autotuner cache lookup for a plan's stencil class and size (tune.cpp).
 bool tune_lookup_plan(const stencil_plan_s* pl, bool batched, int* depth, int* seg);
+// Prepared plans through the persistent batch kernel (batch_host.cpp).
+stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::vector<const void*>& ins,
+                         const std::vector<void*>& outs, const std::vector<void*>& wsg, hipStream_t s);
 }  // namespace stencil_impl
 
 struct stencil_plan_s {
@@ -56,6 +59,7 @@ struct stencil_plan_s {
   // plain kernel taps (offset, weight), dense-box order
   std::vector<int64_t> tap_off;
   std::vector<double> tap_w;
+  bool persistent = false;  // all passes in one persistent launch
   bool plan_ok_3d(int) const { return r <= 2; }
 };
 

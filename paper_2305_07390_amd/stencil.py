@@ -181,6 +181,14 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise StencilLibraryMissing(
             f"{path} not found: build it with `python -m paper_2305_07390_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname as the system's.
+    # Loading torch first makes the library bind to that one; loading the
+    # library first would bring a second HIP/HSA runtime into the process,
+    # and the second to initialise finds no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover - the library works without torch
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGNATURES.items():
         fn = getattr(lib, name)

@@ -1,0 +1,32 @@
+"""One persistent launch for all passes of a grid (inter-pass grid
+synchronisation through the count of finished tiles): the same result as the
+pass-per-launch schedule and the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_07390_amd import stencil as st
+from paper_2305_07390_amd import workloads as wl
+from tests.gpu_util import gpu_sweep
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("2d5pt_star_r1", (300, 700), 40, np.float64),
+    ("2d25pt_box_r2", (257, 1100), 23, np.float32),
+    ("2d13pt_star_r3", (512, 512), 17, np.float64),
+    ("3d7pt_star_r1", (40, 70, 130), 9, np.float64),
+    ("3d13pt_star_r2", (33, 64, 100), 7, np.float32),
+]
+
+
+@pytest.mark.parametrize("name,interior,T,dtype", CASES, ids=[c[0] + "_" + np.dtype(c[3]).name for c in CASES])
+def test_persistent_equals_oracle(name, interior, T, dtype):
+    spec = {s.name: s for s in wl.ALL_STENCILS}[name]
+    coeffs = wl.coeffs_for(spec, 61)
+    u0 = wl.make_field(interior, spec.r, seed=62, dtype=dtype)
+    ref = oracle.sweep(coeffs, spec.r, u0, T)
+    got, info = gpu_sweep(coeffs, spec.r, u0, T, flags=st.STENCIL_FLAG_PERSISTENT, repeats=2,
+                          return_info=True)
+    assert info["passes"] >= 2, info
+    np.testing.assert_array_equal(got, ref)
