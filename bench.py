@@ -189,6 +189,27 @@ def bench_3d(torch, np, stencil, workloads, n=512, T=200):
             round(total_u / total_t / 1e9, 1), "per_stencil": rows}
 
 
+def bench_persistent(torch, np, stencil, problems, xs, ys):
+    """The 2D suite with every pass of a grid in one persistent launch
+    (inter-pass synchronisation through the grid-wide tile count)."""
+    rows, total_t, total_u = [], 0.0, 0
+    for prob, x, y in zip(problems, xs, ys):
+        plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, prob.T,
+                            flags=stencil.STENCIL_FLAG_PERSISTENT)
+        plan.execute(x, y)
+        stencil.stencil_sync()
+        t = timed(torch, lambda: plan.execute(x, y))
+        stencil.stencil_sync()
+        rows.append({"stencil": prob.spec.name, "depth": plan.info["depth"], "passes": plan.info["passes"],
+                     "ms": round(t * 1e3, 2), "gcells_per_s": round(prob.updates / t / 1e9, 1)})
+        total_t += t
+        total_u += prob.updates
+        log(f"  persistent {rows[-1]}")
+        plan.close()
+    return {"workload": "2D single-grid suite, all passes in one persistent launch per grid",
+            "gcells_per_s": round(total_u / total_t / 1e9, 1), "per_stencil": rows}
+
+
 def bench_batch(torch, np, stencil, workloads):
     """128 heterogeneous grids, one batched submission per dtype."""
     probs = workloads.batch_problems()
@@ -228,7 +249,7 @@ def bench_serving(np, torch, stencil, workloads, seconds=3.0, rate=200.0):
     def keep(k, res):
         if k < 8:
             sample[k] = res
-    with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=64, quantum_passes=4) as srv:
+    with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=64) as srv:
         res = serving.serve_open_loop(srv, reqs, arr, on_result=keep)
     s = res["stats"]
     err = 0.0
@@ -406,6 +427,9 @@ def main():
         "copy_bandwidth_GBs": round(B, 1),
         "per_stencil": breakdown,
     }
+    if not args.no_extras:
+        log("2D suite, persistent launches ...")
+        result["suite_2d_persistent"] = bench_persistent(torch, np, stencil, problems, xs, ys)
     del xs, ys
     torch.cuda.empty_cache()
     if not args.no_extras:

@@ -280,13 +280,17 @@ stencil_status stencil_tune_cache_clear(void);
  * round runs the next quantum (at most quantum_passes passes of the request's
  * temporal depth) of every resident request in one stencil_batch_submit, so a
  * request that arrives mid-round starts at the next round and its work shares
- * the device with the others'. Latency is measured from submit to the end of
+ * the device with the others'. A quantum is quantum_passes passes; with
+ * round_target_s > 0 it is at least the request's fair share of a round of
+ * that duration (the throughput measured over past rounds, divided by the
+ * resident requests and the request's cells, in whole passes). Latency is measured from submit to the end of
  * the round that completes the request; results stay on the device until
  * stencil_server_poll collects them. Results equal stencil_run's bit for bit
  * (running T steps as several quanta is the same arithmetic).
  *
  * stencil_server_create: budget > 0, max_slots >= 1; quantum_passes <= 0
- *   means 4. Fails with STENCIL_ERR_DEVICE when the device is unusable.
+ *   means 4; round_target_s <= 0 turns the fair share off. Fails with
+ *   STENCIL_ERR_DEVICE when the device is unusable.
  * stencil_server_submit: STENCIL_ERR_BUDGET if the request alone exceeds the
  *   budget, STENCIL_ERR_INVALID for a bad job (as stencil_plan) or NULL
  *   arguments; otherwise returns a ticket.
@@ -307,6 +311,7 @@ typedef struct {
   int32_t max_slots;         /* resident requests at most */
   int32_t quantum_passes;    /* passes per request per round (<= 0: 4) */
   uint64_t hbm_budget_bytes; /* device memory for resident requests */
+  double round_target_s;     /* > 0: fair share of a round of this duration */
 } stencil_server_config;
 
 typedef struct {

@@ -9,6 +9,7 @@ from __future__ import annotations
 import concurrent.futures as cf
 import os
 import shutil
+import re
 import subprocess
 import sys
 
@@ -38,13 +39,30 @@ def sources():
                   if f.endswith(".hip") or f.endswith(".cpp"))
 
 
-def _compile(src: str) -> str:
+RESOURCE_REPORT = os.path.join(BUILD, "kernel_resources.txt")
+_REMARK = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]|LDS Size \[bytes/block\]):\s*(\S+)")
+
+
+def _resources(stderr: str):
+    """Per-kernel register, scratch and LDS use from the compiler's resource
+    remarks: [(name, {field: value})]."""
+    out, cur = [], None
+    for field, value in _REMARK.findall(stderr):
+        if field == "Function Name":
+            cur = (value, {})
+            out.append(cur)
+        elif cur is not None:
+            cur[1][field.split(" ")[0]] = value
+    return out
+
+
+def _compile(src: str):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *COMMON, *DEVICE_FLAGS, "-c", src, "-o", obj]
+    cmd = [_hipcc(), *COMMON, *DEVICE_FLAGS, "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
-    return obj
+    return obj, _resources(res.stderr)
 
 
 def build(jobs: int | None = None, verbose: bool = True) -> str:
@@ -52,7 +70,14 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
     srcs = sources()
     jobs = jobs or max(1, min(len(srcs), len(os.sched_getaffinity(0))))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        results = list(ex.map(_compile, srcs))
+    objs = [o for o, _ in results]
+    # one line per kernel: name, VGPRs, AGPRs, scratch bytes per lane, LDS
+    with open(RESOURCE_REPORT, "w") as f:
+        for src, (_, kernels) in zip(srcs, results):
+            for name, r in kernels:
+                f.write(f"{os.path.basename(src)} {name} vgpr={r.get('VGPRs')} agpr={r.get('AGPRs')} "
+                        f"scratch={r.get('ScratchSize')} lds={r.get('LDS')}\n")
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)

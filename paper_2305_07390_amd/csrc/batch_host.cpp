@@ -353,17 +353,19 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
       // the fused batch kernel's own depth limit for this variant
       const int cap = batch_max_depth(pl->dtype == STENCIL_F64 ? kF64 : kF32, pl->ndim, pl->r,
                                       pl->pattern);
-      if (pl->depth > cap) {
+      if (cap >= 1 && pl->depth > cap) {
         stencil_plan_destroy(pl);
         pl = nullptr;
         hint.depth = cap;
-        if (cap > 0) status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
-        if (cap <= 0 || status[i] != STENCIL_OK) {
-          // no batched variant: plan for the plain path
-          hint.depth = 0;
-          hint.flags = STENCIL_FLAG_NAIVE;
-          status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
-        }
+        status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+      } else if (cap == 0) {
+        // no batched variant: the job runs alone after the persistent launch,
+        // with the single-grid planner's own segments (enough tiles to fill
+        // the device on its own, unlike the batch's long segments)
+        stencil_plan_destroy(pl);
+        pl = nullptr;
+        hint.tile[0] = 0;
+        status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
       }
     }
     if (status[i] == STENCIL_OK) {

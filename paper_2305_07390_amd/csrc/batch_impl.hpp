@@ -80,12 +80,15 @@ __device__ __forceinline__ void pass_buffers(const void* in, void* out, void* ws
   *dst = ((npass - 1 - pass) & 1) == 0 ? out : ws;
 }
 
-// Deepest compiled depth of a batched variant. All variants share one kernel
-// (and so one register allocation), where radius-2 star tiles at depth 8
-// spill; they stop at 7 there.
+// Deepest compiled depth of a batched variant (0: not in the batch kernel;
+// such jobs run with their single-grid kernels after it). All variants share
+// one kernel, and so one register allocation, where some tiles spill at their
+// single-grid depth: 2D radius-2 stars stop at 7 (FP64) and 6 (FP32), and
+// FP64 3D radius-2 tiles (4 x 2 cells per lane) are left out.
 constexpr int batch_depth_c(int dtype, int ndim, int r, int shape) {
-  return ndim == 2 ? ((r == 2 && shape == kStar) ? 7 : max_depth_c(r, shape))
-                   : tb3d::max_depth_c(dtype, r, shape);
+  if (ndim == 2) return (r == 2 && shape == kStar) ? (dtype == kF64 ? 7 : 6) : max_depth_c(r, shape);
+  if (dtype == kF64 && r == 2) return 0;
+  return tb3d::max_depth_c(dtype, r, shape);
 }
 
 // One wave tile of a 2D job (the tb2d strip/segment decomposition).
@@ -123,7 +126,13 @@ __device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int ti
       X0 = R + (kWave - HL) * V + (strip - 1) * (kWave - 2 * HL) * V - HL * V;
       la = HL; lb = kWave - HL;
     }
-    tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0, Y1, d);
+    // Full-depth passes (all but a job's last) get the depth as a constant,
+    // so the level loop unrolls without per-level checks, as in the
+    // single-grid kernel; the remainder pass takes it at run time.
+    if (d == DEPTH)
+      tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0, Y1, DEPTH);
+    else
+      tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0, Y1, d);
   }
 }
 
@@ -133,7 +142,8 @@ __device__ __forceinline__ void run_3d(const BatchJob<Real>& J, int pass, int ti
   constexpr int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 3, R, SHAPE);
   if constexpr (DEPTH > 0) {
     using namespace tb3d;
-    using FL = FaceLayout<R>;
+    constexpr int BY = cells_y(sizeof(Real) == 8, R);
+    using FL = FaceLayout<R, BY>;
     constexpr int KB = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
     Real* faces = (Real*)lds;
     Real* xchg = faces + kRing * FL::kPerPlane;
@@ -151,10 +161,13 @@ __device__ __forceinline__ void run_3d(const BatchJob<Real>& J, int pass, int ti
     const int rem = tile - seg * sx * sy;
     const int ty = rem / sx;
     const int tx = rem - ty * sx;
-    const Tb3dGeom g = tb3d_geom<R>(tx, ty, sx, sy, P, Qy, uni(J.hx), uni(J.hy));
+    const Tb3dGeom g = tb3d_geom<R, BY>(tx, ty, sx, sy, P, Qy, uni(J.hx), uni(J.hy));
     const int Zs0 = seg * seg_len;
     const int Zs1 = (Zs0 + seg_len < Qz) ? Zs0 + seg_len : Qz;
-    tb3d_tile<Real, R, SHAPE, DEPTH>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, d, faces, xchg);
+    if (d == DEPTH)
+      tb3d_tile<Real, R, SHAPE, DEPTH, 2>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, DEPTH, faces, xchg);
+    else
+      tb3d_tile<Real, R, SHAPE, DEPTH, 2>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, d, faces, xchg);
   }
 }
 

@@ -92,7 +92,7 @@ bool classify(int ndim, int r, const double* c, int* pattern, int* points) {
 int default_depth_2d(int r, int pattern, int dtype) {
   const int maxd = tb2d_max_depth(dtype, r, pattern);
   int d;
-  if (pattern == STENCIL_STAR) d = r == 1 ? 12 : r == 2 ? 8 : r == 3 ? 4 : 3;
+  if (pattern == STENCIL_STAR) d = r == 1 ? 12 : r == 2 ? 8 : r == 3 ? 4 : 2;
   else if (pattern == STENCIL_BOX) d = r == 1 ? 8 : r == 2 ? 4 : r == 3 ? 3 : 2;
   else d = maxd;
   return std::min(d, maxd);
@@ -145,20 +145,23 @@ void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
 // HBM-bound at every depth the registers allow).
 int default_depth_3d(int r, int pattern, int dtype) { return tb3d_max_depth(dtype, r, pattern); }
 
+// Redundant lanes per side of a 3D tile along an axis with B cells per lane.
+int halo_lanes_3d(int depth, int r, int B) { return (depth * r + B - 1) / B; }
+
 void plan_3d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
-  constexpr int B = 4, L = 16, T = L * B;
-  const int H = (depth * p->r + B - 1) / B;
-  auto strips = [&](int64_t n) {
+  constexpr int L = 16;  // lanes along x and along y
+  const int BX = 4, BY = tb3d_cells_y(p->dtype == STENCIL_F64 ? kF64 : kF32, p->r);
+  auto strips = [&](int64_t n, int B, int H) {
     const int64_t side = (int64_t)(L - H) * B, mid = (int64_t)(L - 2 * H) * B;
     int64_t k = 0;
-    if (n == T) return 1;  // one tile exactly covers the interior
+    if (n == (int64_t)L * B) return 1;  // one tile exactly covers the interior
     if (n > 2 * side) k = (n - 2 * side + mid - 1) / mid;
     return (int)(2 + k);
   };
-  p->hx = p->hy = H;
-  p->sx = strips(p->n[2]);
-  p->sy = strips(p->n[1]);
-  (void)T;
+  p->hx = halo_lanes_3d(depth, p->r, BX);
+  p->hy = halo_lanes_3d(depth, p->r, BY);
+  p->sx = strips(p->n[2], BX, p->hx);
+  p->sy = strips(p->n[1], BY, p->hy);
   const int64_t Qz = p->ext[0];
   const int64_t xy = (int64_t)p->sx * p->sy;
   int seg;
@@ -418,10 +421,11 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
       int depth = (hint && hint->depth > 0) ? hint->depth : default_depth_3d(radius, p->pattern, dtype);
       if (depth > maxd) depth = maxd;
       if ((int64_t)depth > T) depth = (int)T;
-      const int H = (depth * radius + 3) / 4;
-      // tiles of 64 x 64 interior cells; each needs its redundant margins inside
-      if (maxd >= 1 && depth >= 1 && p->n[2] >= 64 && p->n[1] >= 64 && 2 * H < 16 &&
-          p->plan_ok_3d(depth)) {
+      const int by = tb3d_cells_y(dtype == STENCIL_F64 ? kF64 : kF32, radius);
+      const int hx = halo_lanes_3d(depth, radius, 4), hy = halo_lanes_3d(depth, radius, by);
+      // tiles of 64 x 16*by interior cells; each needs its redundant margins inside
+      if (maxd >= 1 && depth >= 1 && p->n[2] >= 64 && p->n[1] >= 16 * by && 2 * hx < 16 &&
+          2 * hy < 16 && p->plan_ok_3d(depth)) {
         DeviceInfo di = device_info();
         const int cus = di.ok ? di.cus : 256;
         p->scheme = STENCIL_SCHEME_BLOCKED_3D;

@@ -134,6 +134,9 @@ int tb2d_cols_per_lane(int dtype);
 
 hipError_t naive_launch(int dtype, const void* params, int64_t cells, hipStream_t stream);
 
+// Cells per lane along y of the 3D tiles for (dtype, radius): the tile is
+// 64 x 16 * that.
+int tb3d_cells_y(int dtype, int r);
 hipError_t tb3d_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
                        hipStream_t stream);
 int tb3d_max_depth(int dtype, int r, int shape);

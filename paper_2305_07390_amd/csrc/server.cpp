@@ -38,7 +38,8 @@ struct Request {
   size_t bytes = 0;  // one padded grid
   size_t need = 0;   // device bytes held while resident
   int64_t remaining = 0;
-  int64_t quantum = 1;  // steps per round
+  int64_t depth = 1;    // steps per pass of the batched plan
+  int64_t cells = 1;
   char* dev = nullptr;  // two padded grids
   int cur = 0;          // which half holds the current state
   RState state = RState::kQueued;
@@ -62,6 +63,7 @@ struct stencil_server_s {
   std::vector<Request*> resident;  // admitted, not yet collected
   std::map<uint64_t, std::unique_ptr<Request>> all;
   uint64_t next_ticket = 1;
+  double rate = 3.0e11;  // cell-updates per second, running estimate over rounds
   bool stop = false;
   bool pending_inputs = false;  // copies enqueued since the last round started
   std::thread worker;
@@ -90,6 +92,14 @@ void finish_locked(stencil_server_s* srv, Request* r, RState s, stencil_status e
   } else {
     srv->st.failed++;
   }
+}
+
+// Whether the head of the queue can be admitted now. mu held.
+bool admissible_locked(const stencil_server_s* srv) {
+  if (srv->queue.empty()) return false;
+  const Request* r = srv->queue.front();
+  return (int)srv->resident.size() < srv->cfg.max_slots &&
+         srv->st.hbm_in_use + r->need <= srv->cfg.hbm_budget_bytes;
 }
 
 // Admit queued requests in arrival order while a slot and the budget allow;
@@ -141,16 +151,28 @@ void scheduler(stencil_server_s* srv) {
     if (round.empty()) {
       if (srv->stop) break;
       srv->cv_done.notify_all();  // T = 0 requests admitted just now
-      srv->cv_work.wait(lock, [&] { return srv->stop || !srv->queue.empty(); });
+      // Sleep until a queued request fits (a submission, or a collection
+      // that frees a slot and memory). Waiting on "queue not empty" alone
+      // would return at once while the head does not fit, and the loop would
+      // spin holding the lock that submit and collect need.
+      srv->cv_work.wait(lock, [&] { return srv->stop || admissible_locked(srv); });
       if (srv->stop) break;
       continue;
     }
-    // one quantum of every resident request, in one batched launch
+    // one quantum of every resident request, in one batched launch: each
+    // request's fair share of the round's work, in whole passes
     std::vector<stencil_job> jobs(round.size());
     std::vector<int64_t> steps(round.size());
+    const double share = srv->cfg.round_target_s > 0
+                             ? srv->cfg.round_target_s * srv->rate / (double)round.size()
+                             : 0.0;
+    double round_updates = 0;
     for (size_t k = 0; k < round.size(); ++k) {
       Request* r = round[k];
-      steps[k] = std::min(r->remaining, r->quantum);
+      int64_t q = (int64_t)(share / (double)r->cells) / r->depth * r->depth;
+      q = std::max<int64_t>(q, (int64_t)srv->cfg.quantum_passes * r->depth);
+      steps[k] = std::min(r->remaining, q);
+      round_updates += (double)steps[k] * (double)r->cells;
       jobs[k] = r->job;
       jobs[k].T = steps[k];
       jobs[k].in = r->grid(r->cur);
@@ -191,6 +213,13 @@ void scheduler(stencil_server_s* srv) {
     lock.lock();
     srv->st.rounds++;
     srv->st.busy_s += busy;
+    if (st == STENCIL_OK && busy > 0) {
+      // throughput of this round, smoothed; small rounds under-fill the
+      // device, so only rounds near the target duration update it upward
+      const double r_now = round_updates / busy;
+      if (srv->cfg.round_target_s <= 0 || busy >= 0.5 * srv->cfg.round_target_s || r_now < srv->rate)
+        srv->rate = 0.7 * srv->rate + 0.3 * r_now;
+    }
     for (size_t k = 0; k < round.size(); ++k) {
       Request* r = round[k];
       if (st != STENCIL_OK || js[k] != STENCIL_OK) {
@@ -270,6 +299,7 @@ stencil_status stencil_server_create(const stencil_server_config* config, stenci
   if (!srv) return fail(STENCIL_ERR_NOMEM, "host allocation failed");
   srv->cfg = *config;
   if (srv->cfg.quantum_passes <= 0) srv->cfg.quantum_passes = 4;
+  if (!(srv->cfg.round_target_s > 0)) srv->cfg.round_target_s = 0.0;
   std::memset(&srv->st, 0, sizeof(srv->st));
   int prev = 0;
   (void)hipGetDevice(&prev);
@@ -316,7 +346,8 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
     depth = std::max(1, std::min(depth, batch_max_depth(dt, pl->ndim, pl->r, pl->pattern)));
   else
     depth = 1;
-  r->quantum = (int64_t)srv->cfg.quantum_passes * std::max(1, depth);
+  r->depth = std::max(1, depth);
+  r->cells = std::max<int64_t>(1, pl->cells);
   r->coeffs = pl->coeffs;
   stencil_plan_destroy(pl);
   if (r->need > srv->cfg.hbm_budget_bytes) {

@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
 // values per lane). The general pattern (runtime zero skipping) is a fallback;
 // for r >= 3 it has no blocked variant.
 constexpr int max_depth_c(int r, int shape) {
-  if (shape == kStar) return r == 1 ? 12 : r == 2 ? 8 : r == 3 ? 4 : 3;
+  if (shape == kStar) return r == 1 ? 12 : r == 2 ? 8 : r == 3 ? 4 : 2;
   if (shape == kBox) return r == 1 ? 8 : r == 2 ? 5 : r == 3 ? 3 : 2;
   return r == 1 ? 3 : r == 2 ? 2 : 0;
 }

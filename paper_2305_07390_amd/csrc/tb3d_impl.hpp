@@ -5,9 +5,10 @@
 //
 // Decomposition: overlapped "SM tiling" with N.5-D streaming along z (paper
 // Sections 2.1.2-2.1.3, 3.5-D blocking; Section 4.1 SM tiling):
-//   * One workgroup of four waves owns an xy tile of 64 x 64 cells and streams
-//     a z segment of it. The 256 lanes form a 16 x 16 grid; lane (lx, ly) holds
-//     a 4 x 4 block of cells (x = 4 lx .. 4 lx + 3, y = 4 ly .. 4 ly + 3).
+//   * One workgroup of four waves owns an xy tile of 64 x (16 BY) cells and
+//     streams a z segment of it. The 256 lanes form a 16 x 16 grid; lane
+//     (lx, ly) holds a 4 x BY block of cells (x = 4 lx .. 4 lx + 3,
+//     y = BY ly .. BY ly + BY - 1), BY = 4 (2 for FP64 radius 2).
 //     Wave w holds lane rows 4w .. 4w + 3, so one 16-lane DPP row is one lane
 //     row of the tile.
 //   * Time levels form a skewed wavefront along z: when input plane z arrives,
@@ -48,15 +49,20 @@ using namespace stencil_dev;
 namespace tb3d {
 
 constexpr int BX = 4;      // cells per lane along x
-constexpr int BY = 4;      // cells per lane along y
 constexpr int LX = 16;     // lanes along x (one DPP row)
 constexpr int LY = 16;     // lanes along y (four waves)
 constexpr int TX = LX * BX;  // tile extent in x (64)
-constexpr int TY = LY * BY;  // tile extent in y (64)
 constexpr int kThreads = LX * LY;
+
+// Cells per lane along y (BY; the tile is LY * BY tall). FP64 radius-2 tiles
+// hold 4 x 2 cells per lane: with 4 x 4 their partial planes and extended
+// neighbourhoods do not fit the register file even at depth 1.
+constexpr int cells_y(bool f64, int r) { return (f64 && r >= 2) ? 2 : 4; }
 constexpr int kRing = 16;  // planes in the face queue (power of two)
 
 constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
+constexpr int gcd_3d(int a, int b) { return b == 0 ? a : gcd_3d(b, a % b); }
+constexpr int lcm_3d(int a, int b) { return a / gcd_3d(a, b) * b; }
 
 // DPP row shifts by one lane inside each 16-lane row; lanes whose source is
 // outside the row keep `old`.
@@ -85,8 +91,9 @@ __device__ __forceinline__ float dpp_keep(float old, float v) {
 //   right [R][TY]            x = X0 + TX + c
 //   top   [R][TX + 2R]       y = Y0 - R + c, x = X0 - R + i
 //   bottom[R][TX + 2R]       y = Y0 + TY + c
-template <int R>
+template <int R, int BY>
 struct FaceLayout {
+  static constexpr int TY = LY * BY;
   static constexpr int kLeft = 0;
   static constexpr int kRight = R * TY;
   static constexpr int kTop = 2 * R * TY;
@@ -106,16 +113,24 @@ struct XchgLayout {
   static constexpr int kBufs = (R == 1) ? 2 : 1;
 };
 
-template <typename Real, int R>
+template <typename Real, int R, int BY = cells_y(sizeof(Real) == 8, R)>
 struct Lds {
-  static constexpr int kFaces = kRing * FaceLayout<R>::kPerPlane;
+  static constexpr int kFaces = kRing * FaceLayout<R, BY>::kPerPlane;
   static constexpr int kXchg = XchgLayout<R>::kBufs * XchgLayout<R>::kPerBuf;
   static constexpr size_t kBytes = (size_t)(kFaces + kXchg) * sizeof(Real);
 };
 
-template <typename Real, int R, int DEPTH>
+// Planes in flight per lane (loaded Z0 - 1 iterations before use). Deeper
+// rings hide more HBM latency (one workgroup per CU has little else to hide
+// it with); FP64 star and box variants at depth 2 keep 2, the most their
+// registers allow without spilling.
+constexpr int plane_ring(bool f64, int r, int shape, int depth) {
+  return (f64 && shape != kGeneral && (depth >= 2 || (r >= 2 && shape == kBox))) ? 2 : 4;
+}
+
+template <typename Real, int R, int DEPTH, int Z0_, int BY>
 struct State {
-  static constexpr int Z0 = 2;  // plane prefetch ring: one plane ahead
+  static constexpr int Z0 = Z0_;  // plane prefetch ring
   Real L0[Z0][BY][BX];
   Real A[DEPTH][2 * R][BY][BX];
   Real F[Z0][3];  // face values this lane loads for planes in flight (<= 3 per lane)
@@ -135,7 +150,7 @@ struct Tile {
   int n_f;
 };
 
-template <typename Real, int R, int SHAPE>
+template <typename Real, int R, int SHAPE, int BY>
 __device__ __forceinline__ void add_plane(Real (&acc)[BY][BX], const Real (&ext)[BY + 2 * R][BX + 2 * R],
                                           const Real* __restrict__ w, int dz) {
   constexpr int SIDE = 2 * R + 1;
@@ -155,13 +170,13 @@ __device__ __forceinline__ void add_plane(Real (&acc)[BY][BX], const Real (&ext)
 }
 
 // One input plane through all levels (iteration i, phase ph).
-template <typename Real, int R, int SHAPE, int DEPTH, bool GENERAL>
-__device__ __forceinline__ void plane_step(State<Real, R, DEPTH>& st, const Tile& t,
+template <typename Real, int R, int SHAPE, int DEPTH, bool GENERAL, int Z0, int BY>
+__device__ __forceinline__ void plane_step(State<Real, R, DEPTH, Z0, BY>& st, const Tile& t,
                                            const Real* __restrict__ w, Real* faces, Real* xchg,
                                            const int lx, const int ly, const int ph, const int i) {
-  using FL = FaceLayout<R>;
+  using FL = FaceLayout<R, BY>;
+  constexpr int TY = FL::TY;
   using XL = XchgLayout<R>;
-  constexpr int Z0 = State<Real, R, DEPTH>::Z0;
   constexpr int S = sizeof(Real);
   const int lane_id_t = ly * LX + lx;
 
@@ -262,7 +277,7 @@ __device__ __forceinline__ void plane_step(State<Real, R, DEPTH>& st, const Tile
       const int o = u - R;
       const int sl = ph % (2 * R);
       const bool halo = GENERAL && ((o < R) || (o >= Qz - R));
-      if (ok && !halo) add_plane<Real, R, SHAPE>(st.A[s - 1][sl], ext, w, R);
+      if (ok && !halo) add_plane<Real, R, SHAPE, BY>(st.A[s - 1][sl], ext, w, R);
 #pragma unroll
       for (int j = 0; j < BY; ++j)
 #pragma unroll
@@ -289,7 +304,7 @@ __device__ __forceinline__ void plane_step(State<Real, R, DEPTH>& st, const Tile
 #pragma unroll
               for (int q = 0; q < BX; ++q) st.A[s - 1][sl][j][q] = Real(0);
           }
-          add_plane<Real, R, SHAPE>(st.A[s - 1][sl], ext, w, dz);
+          add_plane<Real, R, SHAPE, BY>(st.A[s - 1][sl], ext, w, dz);
         }
       }
     }
@@ -314,9 +329,10 @@ __device__ __forceinline__ void plane_step(State<Real, R, DEPTH>& st, const Tile
 struct Tb3dGeom {
   int X0, lxa, lxb, Y0, lya, lyb;
 };
-template <int R>
+template <int R, int BY>
 __device__ __forceinline__ Tb3dGeom tb3d_geom(int tx, int ty, int sx, int sy, int P, int Qy, int HX,
                                               int HY) {
+  constexpr int TY = LY * BY;
   Tb3dGeom g;
   // a single tile exactly as wide (tall) as the interior has halo on both sides
   if (sx == 1) { g.X0 = R; g.lxa = 0; g.lxb = LX; }
@@ -332,14 +348,17 @@ __device__ __forceinline__ Tb3dGeom tb3d_geom(int tx, int ty, int sx, int sy, in
 
 // One workgroup tile of one pass: d (<= DEPTH) levels from src to dst over the
 // planes [Zs0, Zs1) of the xy tile g. Every thread of the workgroup calls it.
-template <typename Real, int R, int SHAPE, int DEPTH>
+// Z0: planes in flight (plane_ring by default; the fused batch kernel, whose
+// one register allocation serves every variant, passes 2).
+template <typename Real, int R, int SHAPE, int DEPTH,
+          int Z0 = plane_ring(sizeof(Real) == 8, R, SHAPE, DEPTH), int BY = cells_y(sizeof(Real) == 8, R)>
 __device__ __forceinline__ void tb3d_tile(const Real* __restrict__ w, const void* src, void* dst,
                                           const int P, const int Qy, const int Qz,
                                           const Tb3dGeom g, const int Zs0, const int Zs1,
                                           const int d, Real* faces, Real* xchg) {
-  using FL = FaceLayout<R>;
-  constexpr int Z0 = State<Real, R, DEPTH>::Z0;
-  constexpr int UNROLL = (2 * R) % Z0 == 0 ? 2 * R : 2 * R * Z0;
+  using FL = FaceLayout<R, BY>;
+  constexpr int TY = FL::TY;
+  constexpr int UNROLL = lcm_3d(2 * R, Z0);
   constexpr int S = sizeof(Real);
   const int tid = threadIdx.x;
   const int lx = tid % LX;
@@ -392,7 +411,7 @@ __device__ __forceinline__ void tb3d_tile(const Real* __restrict__ w, const void
     }
   }
 
-  State<Real, R, DEPTH> st;
+  State<Real, R, DEPTH, Z0, BY> st;
 #pragma unroll
   for (int zz = 0; zz < Z0; ++zz) {
 #pragma unroll
@@ -411,7 +430,7 @@ __device__ __forceinline__ void tb3d_tile(const Real* __restrict__ w, const void
 #pragma unroll
         for (int q = 0; q < BX; ++q) st.A[s][sl][j][q] = Real(0);
 
-  // prologue: planes 0 and 1 (blocks and faces), face queue slot of plane 0
+  // prologue: the first Z0 planes (blocks and faces), face queue slot of plane 0
   __syncthreads();  // the previous tile is done with the LDS queues
 #pragma unroll
   for (int p = 0; p < Z0; ++p) {
@@ -448,24 +467,25 @@ __device__ __forceinline__ void tb3d_tile(const Real* __restrict__ w, const void
 #pragma unroll
     for (int ph = 0; ph < UNROLL; ++ph)
       if (base + ph < t.n_iter)
-        plane_step<Real, R, SHAPE, DEPTH, true>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
+        plane_step<Real, R, SHAPE, DEPTH, true, Z0, BY>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
   }
   for (; base < i_b; base += UNROLL) {
 #pragma unroll
     for (int ph = 0; ph < UNROLL; ++ph)
-      plane_step<Real, R, SHAPE, DEPTH, false>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
+      plane_step<Real, R, SHAPE, DEPTH, false, Z0, BY>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
   }
   for (; base < t.n_iter; base += UNROLL) {
 #pragma unroll
     for (int ph = 0; ph < UNROLL; ++ph)
       if (base + ph < t.n_iter)
-        plane_step<Real, R, SHAPE, DEPTH, true>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
+        plane_step<Real, R, SHAPE, DEPTH, true, Z0, BY>(st, t, w, faces, xchg, lx, ly, ph, base + ph);
   }
 }
 
 template <typename Real, int R, int SHAPE, int DEPTH>
 __global__ __launch_bounds__(kThreads) void tb3d_kernel(const Tb3dParams<Real> a) {
-  using FL = FaceLayout<R>;
+  constexpr int BY = cells_y(sizeof(Real) == 8, R);
+  using FL = FaceLayout<R, BY>;
   extern __shared__ char lds_raw[];
   Real* faces = (Real*)lds_raw;
   Real* xchg = faces + kRing * FL::kPerPlane;
@@ -475,7 +495,7 @@ __global__ __launch_bounds__(kThreads) void tb3d_kernel(const Tb3dParams<Real> a
     const int rem = tile - seg * a.sx * a.sy;
     const int ty = rem / a.sx;
     const int tx = rem - ty * a.sx;
-    const Tb3dGeom g = tb3d_geom<R>(tx, ty, a.sx, a.sy, P, Qy, a.hx, a.hy);
+    const Tb3dGeom g = tb3d_geom<R, BY>(tx, ty, a.sx, a.sy, P, Qy, a.hx, a.hy);
     const int Zs0 = seg * a.seg_len;
     const int Zs1 = (Zs0 + a.seg_len < Qz) ? Zs0 + a.seg_len : Qz;
     tb3d_tile<Real, R, SHAPE, DEPTH>(a.w, a.src, a.dst, P, Qy, Qz, g, Zs0, Zs1, DEPTH, faces, xchg);
@@ -484,12 +504,12 @@ __global__ __launch_bounds__(kThreads) void tb3d_kernel(const Tb3dParams<Real> a
 
 // Deepest compiled variant per (dtype, radius, shape) that compiles without
 // scratch spills: the partial planes of every level live in registers
-// (2r planes x 16 cells per lane per level).
+// (2r planes x BX x BY cells per lane per level).
 constexpr int max_depth_c(int dtype, int r, int shape) {
   if (dtype == kF64) {
-    if (shape == kStar) return r == 1 ? 2 : 0;
-    if (shape == kBox) return r == 1 ? 2 : 0;
-    return r == 1 ? 1 : 0;
+    if (shape == kStar) return 2;
+    if (shape == kBox) return r == 1 ? 2 : 1;
+    return 1;
   }
   if (shape == kStar) return r == 1 ? 4 : r == 2 ? 2 : 0;
   if (shape == kBox) return r == 1 ? 3 : 0;

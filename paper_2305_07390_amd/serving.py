@@ -17,8 +17,10 @@ from . import stencil as st
 class Server:
     """Context-managed native server on one device."""
 
-    def __init__(self, hbm_budget_bytes: int, max_slots: int, quantum_passes: int = 0, device: int = 0):
-        self.handle = st.stencil_server_create(hbm_budget_bytes, max_slots, quantum_passes, device)
+    def __init__(self, hbm_budget_bytes: int, max_slots: int, quantum_passes: int = 0, device: int = 0,
+                 round_target_s: float = 0.0):
+        self.handle = st.stencil_server_create(hbm_budget_bytes, max_slots, quantum_passes, device,
+                                               round_target_s)
 
     def submit(self, coeffs, radius: int, interior, T: int, field: np.ndarray) -> int:
         return st.stencil_server_submit(self.handle, coeffs, radius, interior, T, field)

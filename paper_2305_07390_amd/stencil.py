@@ -30,6 +30,7 @@ STENCIL_F64 = 1
 
 STENCIL_FLAG_NAIVE = 1
 STENCIL_FLAG_NO_CACHE = 2
+STENCIL_FLAG_PERSISTENT = 4
 
 STENCIL_TUNE_BATCH = 1
 STENCIL_TUNE_FORCE = 2
@@ -113,7 +114,8 @@ class stencil_tune_result(ctypes.Structure):
 
 class stencil_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32),
-                ("quantum_passes", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64)]
+                ("quantum_passes", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("round_target_s", ctypes.c_double)]
 
 
 class stencil_server_statistics(ctypes.Structure):
@@ -352,8 +354,9 @@ def use_tuned_defaults(path: str = TUNE_CACHE_PATH) -> int:
 
 
 def stencil_server_create(hbm_budget_bytes: int, max_slots: int, quantum_passes: int = 0,
-                          device: int = 0):
+                          device: int = 0, round_target_s: float = 0.0):
     cfg = stencil_server_config()
+    cfg.round_target_s = float(round_target_s)
     cfg.device = int(device)
     cfg.max_slots = int(max_slots)
     cfg.quantum_passes = int(quantum_passes)

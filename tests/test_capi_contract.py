@@ -211,3 +211,13 @@ def test_batch_rejects_shared_outputs_before_device_work():
     with pytest.raises(st.StencilError) as e:
         st.stencil_batch_submit(specs, 0)
     assert e.value.status == st.STENCIL_ERR_INVALID
+
+
+def test_python_constants_mirror_header_defines():
+    text = open(HEADER).read()
+    defines = dict(re.findall(r"#define (STENCIL_[A-Z_0-9]+) (\d+)", text))
+    assert defines, "no #define in the header"
+    for name, value in defines.items():
+        if name.startswith("STENCIL_MODEL_"):
+            continue  # exposed as MODEL_* in the binding
+        assert getattr(st, name) == int(value), name

@@ -34,7 +34,9 @@ def _small_requests(n, seed, dtype):
 @pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
 def test_served_results_equal_alone(dtype):
     reqs, arr = _small_requests(24, seed=21, dtype=dtype)
-    with serving.Server(hbm_budget_bytes=8 << 30, max_slots=16, quantum_passes=2) as srv:
+    # one pass per request per round, so requests take several rounds and
+    # overlap with later arrivals
+    with serving.Server(hbm_budget_bytes=8 << 30, max_slots=16, quantum_passes=1) as srv:
         out = serving.serve_open_loop(srv, reqs, arr, keep_results=True)
     assert not out["rejected"]
     s = out["stats"]
@@ -86,6 +88,16 @@ def test_admission_respects_budget_and_slots():
         s = srv.stats()
     assert s["rejected"] == 1 and s["completed"] == 6
     assert s["hbm_peak"] <= budget and s["max_active"] <= 2
+
+
+def test_work_share_quantum_equals_alone():
+    """Rounds of a fair share of 5 ms of work per request: same results."""
+    reqs, arr = _small_requests(16, seed=44, dtype=np.float32)
+    with serving.Server(hbm_budget_bytes=8 << 30, max_slots=16, round_target_s=0.005) as srv:
+        out = serving.serve_open_loop(srv, reqs, arr, keep_results=True)
+    assert out["stats"]["completed"] == len(reqs)
+    for (prob, field, T), got in zip(reqs, out["results"]):
+        np.testing.assert_array_equal(got, _alone(prob, field, T))
 
 
 def test_percentiles_match_latencies():
