@@ -21,10 +21,22 @@ int batch_max_depth(int dtype, int ndim, int r, int shape) {
   return batch::batch_depth_c(dtype, ndim, r, shape);
 }
 
-size_t batch_lds_3d(int dtype, int r) {
+namespace {
+template <typename Real, int R>
+size_t lds_3d(int shape) {
+  using namespace tb3d;
+  switch (shape) {
+    case kStar: return Lds<Real, R, cells_y(sizeof(Real) == 8, R, kStar)>::kBytes;
+    case kBox: return Lds<Real, R, cells_y(sizeof(Real) == 8, R, kBox)>::kBytes;
+    default: return Lds<Real, R, cells_y(sizeof(Real) == 8, R, kGeneral)>::kBytes;
+  }
+}
+}  // namespace
+
+size_t batch_lds_3d(int dtype, int r, int shape) {
   const bool f64 = dtype == kF64;
-  if (r == 1) return f64 ? tb3d::Lds<double, 1>::kBytes : tb3d::Lds<float, 1>::kBytes;
-  if (r == 2) return f64 ? tb3d::Lds<double, 2>::kBytes : tb3d::Lds<float, 2>::kBytes;
+  if (r == 1) return f64 ? lds_3d<double, 1>(shape) : lds_3d<float, 1>(shape);
+  if (r == 2) return f64 ? lds_3d<double, 2>(shape) : lds_3d<float, 2>(shape);
   return 0;
 }
 

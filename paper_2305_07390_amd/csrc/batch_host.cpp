@@ -182,7 +182,7 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     for (int i : g.jobs) {
       const stencil_plan_s* p = plans[i];
       if (p->ndim == 2) m.hq_stride = std::max<int64_t>(m.hq_stride, (int64_t)p->hq_rows * 2 * p->r);
-      else m.lds = std::max(m.lds, batch_lds_3d(d, p->r));
+      else m.lds = std::max(m.lds, batch_lds_3d(d, p->r, p->pattern));
     }
     m.lds = std::max(m.lds, (size_t)(4 * m.hq_stride) * elem);
   }

@@ -142,7 +142,7 @@ __device__ __forceinline__ void run_3d(const BatchJob<Real>& J, int pass, int ti
   constexpr int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 3, R, SHAPE);
   if constexpr (DEPTH > 0) {
     using namespace tb3d;
-    constexpr int BY = cells_y(sizeof(Real) == 8, R);
+    constexpr int BY = cells_y(sizeof(Real) == 8, R, SHAPE);
     using FL = FaceLayout<R, BY>;
     constexpr int KB = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
     Real* faces = (Real*)lds;

@@ -150,7 +150,7 @@ int halo_lanes_3d(int depth, int r, int B) { return (depth * r + B - 1) / B; }
 
 void plan_3d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
   constexpr int L = 16;  // lanes along x and along y
-  const int BX = 4, BY = tb3d_cells_y(p->dtype == STENCIL_F64 ? kF64 : kF32, p->r);
+  const int BX = 4, BY = tb3d_cells_y(p->dtype == STENCIL_F64 ? kF64 : kF32, p->r, p->pattern);
   auto strips = [&](int64_t n, int B, int H) {
     const int64_t side = (int64_t)(L - H) * B, mid = (int64_t)(L - 2 * H) * B;
     int64_t k = 0;
@@ -168,11 +168,26 @@ void plan_3d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
   if (seg_hint > 0) {
     seg = seg_hint;
   } else {
-    // one workgroup per CU (the LDS queues take most of a CU's 160 KB)
-    int64_t nseg = std::max<int64_t>(1, cus / xy);
-    seg = (int)((Qz + nseg - 1) / nseg);
+    // One workgroup per CU (the LDS queues take most of a CU's 160 KB), so
+    // tiles run in rounds of `cus`. A pass costs about (rounds) x (planes a
+    // tile streams: its segment plus the 2 d r warm-up planes); pick the
+    // segment count that minimises it (more, shorter segments fill the last
+    // round better but stream more warm-up planes).
+    const int64_t halo = 2 * (int64_t)depth * p->r;
     const int min_seg = std::max(8, 4 * depth * p->r);
-    if (seg < min_seg) seg = min_seg;
+    int64_t best_cost = -1;
+    seg = (int)Qz;
+    for (int64_t nseg = 1; nseg <= 64; ++nseg) {
+      const int64_t s_len = (Qz + nseg - 1) / nseg;
+      if (s_len < min_seg && nseg > 1) break;
+      const int64_t real_segs = (Qz + s_len - 1) / s_len;
+      const int64_t rounds = (xy * real_segs + cus - 1) / cus;
+      const int64_t cost = rounds * (s_len + halo);
+      if (best_cost < 0 || cost < best_cost) {
+        best_cost = cost;
+        seg = (int)s_len;
+      }
+    }
   }
   const int64_t plane_bytes = p->ext[1] * p->ext[2] * (int64_t)p->elem;
   const int64_t max_planes = ((int64_t)1 << 31) / plane_bytes - 2 * depth * p->r - 4;
@@ -421,7 +436,7 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
       int depth = (hint && hint->depth > 0) ? hint->depth : default_depth_3d(radius, p->pattern, dtype);
       if (depth > maxd) depth = maxd;
       if ((int64_t)depth > T) depth = (int)T;
-      const int by = tb3d_cells_y(dtype == STENCIL_F64 ? kF64 : kF32, radius);
+      const int by = tb3d_cells_y(dtype == STENCIL_F64 ? kF64 : kF32, radius, p->pattern);
       const int hx = halo_lanes_3d(depth, radius, 4), hy = halo_lanes_3d(depth, radius, by);
       // tiles of 64 x 16*by interior cells; each needs its redundant margins inside
       if (maxd >= 1 && depth >= 1 && p->n[2] >= 64 && p->n[1] >= 16 * by && 2 * hx < 16 &&

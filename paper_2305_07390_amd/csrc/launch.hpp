@@ -104,7 +104,7 @@ hipError_t batch_launch(int dtype, const void* params, int grid, size_t lds_byte
 // Deepest compiled depth of a batched variant (0: none), and the LDS bytes a
 // 3D variant needs.
 int batch_max_depth(int dtype, int ndim, int r, int shape);
-size_t batch_lds_3d(int dtype, int r);
+size_t batch_lds_3d(int dtype, int r, int shape);
 hipError_t frame_copy_batch_launch(int dtype, const FrameCopyJob* jobs_dev, int njobs,
                                    hipStream_t stream);
 
@@ -134,9 +134,9 @@ int tb2d_cols_per_lane(int dtype);
 
 hipError_t naive_launch(int dtype, const void* params, int64_t cells, hipStream_t stream);
 
-// Cells per lane along y of the 3D tiles for (dtype, radius): the tile is
-// 64 x 16 * that.
-int tb3d_cells_y(int dtype, int r);
+// Cells per lane along y of the 3D tiles for (dtype, radius, shape): the
+// tile is 64 x 16 * that.
+int tb3d_cells_y(int dtype, int r, int shape);
 hipError_t tb3d_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
                        hipStream_t stream);
 int tb3d_max_depth(int dtype, int r, int shape);

@@ -26,7 +26,7 @@ hipError_t tb3d_launch(int dtype, int r, int shape, int depth, const void* param
   return hipErrorInvalidValue;
 }
 
-int tb3d_cells_y(int dtype, int r) { return tb3d::cells_y(dtype == kF64, r); }
+int tb3d_cells_y(int dtype, int r, int shape) { return tb3d::cells_y(dtype == kF64, r, shape); }
 
 int tb3d_max_depth(int dtype, int r, int shape) {
   (void)dtype;

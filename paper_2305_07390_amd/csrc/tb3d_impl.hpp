@@ -8,7 +8,7 @@
 //   * One workgroup of four waves owns an xy tile of 64 x (16 BY) cells and
 //     streams a z segment of it. The 256 lanes form a 16 x 16 grid; lane
 //     (lx, ly) holds a 4 x BY block of cells (x = 4 lx .. 4 lx + 3,
-//     y = BY ly .. BY ly + BY - 1), BY = 4 (2 for FP64 radius 2).
+//     y = BY ly .. BY ly + BY - 1), BY = 4 or 2 (cells_y).
 //     Wave w holds lane rows 4w .. 4w + 3, so one 16-lane DPP row is one lane
 //     row of the tile.
 //   * Time levels form a skewed wavefront along z: when input plane z arrives,
@@ -54,10 +54,12 @@ constexpr int LY = 16;     // lanes along y (four waves)
 constexpr int TX = LX * BX;  // tile extent in x (64)
 constexpr int kThreads = LX * LY;
 
-// Cells per lane along y (BY; the tile is LY * BY tall). FP64 radius-2 tiles
-// hold 4 x 2 cells per lane: with 4 x 4 their partial planes and extended
-// neighbourhoods do not fit the register file even at depth 1.
-constexpr int cells_y(bool f64, int r) { return (f64 && r >= 2) ? 2 : 4; }
+// Cells per lane along y (BY; the tile is LY * BY tall). FP64 tiles other
+// than the radius-1 box hold 4 x 2 cells per lane: radius 2 does not fit the
+// register file with 4 x 4 even at depth 1, and the 7-point star reaches
+// depth 4 with four planes in flight (636 against 504 GCells/s for 4 x 4 at
+// depth 2 on 512^3); the 27-point box is faster with 4 x 4 at depth 2.
+constexpr int cells_y(bool f64, int r, int shape) { return (f64 && (r >= 2 || shape != kBox)) ? 2 : 4; }
 constexpr int kRing = 16;  // planes in the face queue (power of two)
 
 constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
@@ -113,7 +115,7 @@ struct XchgLayout {
   static constexpr int kBufs = (R == 1) ? 2 : 1;
 };
 
-template <typename Real, int R, int BY = cells_y(sizeof(Real) == 8, R)>
+template <typename Real, int R, int BY>
 struct Lds {
   static constexpr int kFaces = kRing * FaceLayout<R, BY>::kPerPlane;
   static constexpr int kXchg = XchgLayout<R>::kBufs * XchgLayout<R>::kPerBuf;
@@ -125,7 +127,9 @@ struct Lds {
 // it with); FP64 star and box variants at depth 2 keep 2, the most their
 // registers allow without spilling.
 constexpr int plane_ring(bool f64, int r, int shape, int depth) {
-  return (f64 && shape != kGeneral && (depth >= 2 || (r >= 2 && shape == kBox))) ? 2 : 4;
+  if (!f64 || shape == kGeneral) return 4;
+  if (shape == kStar) return (r == 1 || depth == 1) ? 4 : 2;
+  return 2;
 }
 
 template <typename Real, int R, int DEPTH, int Z0_, int BY>
@@ -351,7 +355,7 @@ __device__ __forceinline__ Tb3dGeom tb3d_geom(int tx, int ty, int sx, int sy, in
 // Z0: planes in flight (plane_ring by default; the fused batch kernel, whose
 // one register allocation serves every variant, passes 2).
 template <typename Real, int R, int SHAPE, int DEPTH,
-          int Z0 = plane_ring(sizeof(Real) == 8, R, SHAPE, DEPTH), int BY = cells_y(sizeof(Real) == 8, R)>
+          int Z0 = plane_ring(sizeof(Real) == 8, R, SHAPE, DEPTH), int BY = cells_y(sizeof(Real) == 8, R, SHAPE)>
 __device__ __forceinline__ void tb3d_tile(const Real* __restrict__ w, const void* src, void* dst,
                                           const int P, const int Qy, const int Qz,
                                           const Tb3dGeom g, const int Zs0, const int Zs1,
@@ -484,7 +488,7 @@ __device__ __forceinline__ void tb3d_tile(const Real* __restrict__ w, const void
 
 template <typename Real, int R, int SHAPE, int DEPTH>
 __global__ __launch_bounds__(kThreads) void tb3d_kernel(const Tb3dParams<Real> a) {
-  constexpr int BY = cells_y(sizeof(Real) == 8, R);
+  constexpr int BY = cells_y(sizeof(Real) == 8, R, SHAPE);
   using FL = FaceLayout<R, BY>;
   extern __shared__ char lds_raw[];
   Real* faces = (Real*)lds_raw;
@@ -507,9 +511,9 @@ __global__ __launch_bounds__(kThreads) void tb3d_kernel(const Tb3dParams<Real> a
 // (2r planes x BX x BY cells per lane per level).
 constexpr int max_depth_c(int dtype, int r, int shape) {
   if (dtype == kF64) {
-    if (shape == kStar) return 2;
+    if (shape == kStar) return r == 1 ? 4 : 2;
     if (shape == kBox) return r == 1 ? 2 : 1;
-    return 1;
+    return r == 1 ? 2 : 1;
   }
   if (shape == kStar) return r == 1 ? 4 : r == 2 ? 2 : 0;
   if (shape == kBox) return r == 1 ? 3 : 0;
@@ -525,11 +529,11 @@ hipError_t launch_depth(int depth, const Tb3dParams<Real>* p, int grid, hipStrea
   } else {
     if (depth == D) {
       const void* fn = (const void*)&tb3d_kernel<Real, R, SHAPE, D>;
-      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)Lds<Real, R>::kBytes);
+      constexpr size_t lds = Lds<Real, R, cells_y(sizeof(Real) == 8, R, SHAPE)>::kBytes;
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
       void* args[] = {(void*)p};
-      return hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, Lds<Real, R>::kBytes, s);
+      return hipLaunchKernel(fn, dim3(grid), dim3(kThreads), args, lds, s);
     }
     return launch_depth<Real, R, SHAPE, D - 1>(depth, p, grid, s);
   }
