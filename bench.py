@@ -210,6 +210,28 @@ def bench_persistent(torch, np, stencil, problems, xs, ys):
             "gcells_per_s": round(total_u / total_t / 1e9, 1), "per_stencil": rows}
 
 
+def bench_autotune(torch, np, stencil, problems, xs, ys):
+    """Autotuner on the 2D suite: tune each stencil at its full size (model-
+    pruned candidates timed on the device), then time the plan the cache
+    now picks for a plan without hints, next to the default plan."""
+    stencil.stencil_tune_cache_clear()
+    rows = []
+    for prob, x, y in zip(problems, xs, ys):
+        t0 = time.perf_counter()
+        res = stencil.stencil_tune(prob.coeffs, prob.spec.r, prob.interior, np.float64)
+        tune_s = time.perf_counter() - t0
+        plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, prob.T)
+        plan.execute(x, y)
+        t = timed(torch, lambda: plan.execute(x, y))
+        rows.append({"stencil": prob.spec.name, "depth": plan.info["depth"], "seg_len": plan.info["seg_len"],
+                     "candidates": res["candidates"], "tune_s": round(tune_s, 2),
+                     "gcells_per_s": round(prob.updates / t / 1e9, 1)})
+        log(f"  tuned {rows[-1]}")
+        plan.close()
+    stencil.stencil_tune_cache_clear()
+    return {"workload": "2D single-grid suite, plans from the autotuner's cache", "per_stencil": rows}
+
+
 def bench_batch(torch, np, stencil, workloads):
     """128 heterogeneous grids, one batched submission per dtype."""
     probs = workloads.batch_problems()
@@ -430,6 +452,8 @@ def main():
     if not args.no_extras:
         log("2D suite, persistent launches ...")
         result["suite_2d_persistent"] = bench_persistent(torch, np, stencil, problems, xs, ys)
+        log("2D suite, autotuned ...")
+        result["suite_2d_autotuned"] = bench_autotune(torch, np, stencil, problems, xs, ys)
     del xs, ys
     torch.cuda.empty_cache()
     if not args.no_extras:

@@ -43,6 +43,82 @@ unsigned int* device_error_word() {
   return w;
 }
 
+// Pinned host staging for the control block of a batch, per device. Copies
+// from pinned memory go by DMA; pageable ones go through staging kernels.
+// The buffer is reused: a new upload waits (on the host) until the previous
+// one has left it.
+struct ControlStaging {
+  std::mutex mu;
+  void* buf = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
+ControlStaging* control_staging() {
+  static std::mutex mu;
+  static std::map<int, ControlStaging*> per_device;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = per_device.find(dev);
+  if (it != per_device.end()) return it->second;
+  ControlStaging* cs = new ControlStaging();
+  if (hipEventCreateWithFlags(&cs->done, hipEventDisableTiming) != hipSuccess) {
+    delete cs;
+    return nullptr;
+  }
+  per_device[dev] = cs;
+  return cs;
+}
+
+// Upload `bytes` from `src` to device `dst` on s through the staging buffer
+// (pageable copy if pinned memory is not available).
+hipError_t upload_control(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  ControlStaging* cs = control_staging();
+  if (!cs) return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  std::lock_guard<std::mutex> lock(cs->mu);
+  if (cs->pending) {
+    (void)hipEventSynchronize(cs->done);
+    cs->pending = false;
+  }
+  if (cs->cap < bytes) {
+    if (cs->buf) (void)hipHostFree(cs->buf);
+    cs->buf = nullptr;
+    cs->cap = 0;
+    const size_t want = std::max(bytes * 2, (size_t)1 << 20);
+    if (hipHostMalloc(&cs->buf, want, hipHostMallocDefault) == hipSuccess) cs->cap = want;
+  }
+  if (!cs->buf) return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+  std::memcpy(cs->buf, src, bytes);
+  hipError_t e = hipMemcpyAsync(dst, cs->buf, bytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && hipEventRecord(cs->done, s) == hipSuccess) cs->pending = true;
+  return e;
+}
+
+// Pinned host word per device for reading the error word back by DMA.
+struct PinnedWord {
+  std::mutex mu;
+  unsigned int* p = nullptr;
+};
+
+PinnedWord* pinned_word() {
+  static std::mutex mu;
+  static std::map<int, PinnedWord*> per_device;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = per_device.find(dev);
+  if (it != per_device.end()) return it->second;
+  PinnedWord* w = new PinnedWord();
+  if (hipHostMalloc((void**)&w->p, 256, hipHostMallocDefault) != hipSuccess) {
+    delete w;
+    return nullptr;
+  }
+  per_device[dev] = w;
+  return w;
+}
+
 struct Group {
   int dtype;
   std::vector<int> jobs;  // indices into the batch
@@ -268,7 +344,7 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     put(frames_off[d], frames[d].data(), sizeof(FrameCopyJob) * frames[d].size());
   }
   hipError_t e = hipSuccess;
-  if (!img.empty()) e = hipMemcpyAsync(dev + ctl_lo, img.data(), img.size(), hipMemcpyHostToDevice, s);
+  if (!img.empty()) e = upload_control(dev + ctl_lo, img.data(), img.size(), s);
   stencil_status st = STENCIL_OK;
   if (e != hipSuccess) st = hip_fail(e, "batch control upload");
 
@@ -418,15 +494,27 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
 
 stencil_status stencil_sync(void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
   unsigned int* err = device_error_word();
-  if (!err) return STENCIL_OK;
+  PinnedWord* pw = err ? pinned_word() : nullptr;
   unsigned int h = 0;
-  e = hipMemcpy(&h, err, sizeof(h), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "error word read");
+  hipError_t e;
+  if (pw) {
+    // the read rides on the stream: one synchronisation covers both
+    std::lock_guard<std::mutex> lock(pw->mu);
+    e = hipMemcpyAsync(pw->p, err, sizeof(unsigned int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    h = *pw->p;
+  } else {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    if (err) {
+      e = hipMemcpy(&h, err, sizeof(h), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "error word read");
+    }
+  }
   if (h) {
-    hipMemset(err, 0, sizeof(unsigned int));
+    (void)hipMemset(err, 0, sizeof(unsigned int));
     return fail(STENCIL_ERR_TIMEOUT, "a bounded device wait expired; affected results are undefined");
   }
   return STENCIL_OK;

@@ -93,7 +93,7 @@ int default_depth_2d(int r, int pattern, int dtype) {
   const int maxd = tb2d_max_depth(dtype, r, pattern);
   int d;
   if (pattern == STENCIL_STAR) d = r == 1 ? 12 : r == 2 ? 8 : r == 3 ? 4 : 2;
-  else if (pattern == STENCIL_BOX) d = r == 1 ? 8 : r == 2 ? 4 : r == 3 ? 3 : 2;
+  else if (pattern == STENCIL_BOX) d = r == 1 ? 8 : r == 2 ? 5 : r == 3 ? 3 : 2;
   else d = maxd;
   return std::min(d, maxd);
 }

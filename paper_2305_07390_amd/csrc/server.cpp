@@ -30,11 +30,51 @@ using Clock = std::chrono::steady_clock;
 
 enum class RState { kQueued, kResident, kDone, kFailed };
 
+// Pinned host blocks in power-of-two size classes, reused across requests:
+// copies between pinned memory and the device go by DMA, while pageable
+// copies go through staging kernels that compete with the stencil kernels.
+class PinnedPool {
+ public:
+  ~PinnedPool() {
+    for (auto& kv : free_) (void)hipHostFree(kv.second);
+  }
+  static size_t size_class(size_t bytes) {
+    size_t c = (size_t)1 << 20;
+    while (c < bytes) c <<= 1;
+    return c;
+  }
+  void* get(size_t bytes, size_t* cls) {
+    *cls = size_class(bytes);
+    {
+      std::lock_guard<std::mutex> lock(mu_);
+      auto it = free_.find(*cls);
+      if (it != free_.end()) {
+        void* p = it->second;
+        free_.erase(it);
+        return p;
+      }
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, *cls, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+  }
+  void put(void* p, size_t cls) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(mu_);
+    free_.emplace(cls, p);
+  }
+
+ private:
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;
+};
+
 struct Request {
   uint64_t ticket = 0;
   std::vector<double> coeffs;
   stencil_job job;  // in/out unused; coeffs points into `coeffs`
-  std::vector<char> host_in;
+  void* host_in = nullptr;  // pinned copy of the input (released after the first round)
+  size_t host_cls = 0;
   size_t bytes = 0;  // one padded grid
   size_t need = 0;   // device bytes held while resident
   int64_t remaining = 0;
@@ -73,6 +113,7 @@ struct stencil_server_s {
   bool any_submit = false;
   Clock::time_point first_submit, last_done;
   std::mutex collect_mu;
+  PinnedPool pinned;
 };
 
 namespace {
@@ -113,7 +154,7 @@ void admit_locked(stencil_server_s* srv) {
     const size_t two = 2 * align256(r->bytes);
     hipError_t e = hipMallocAsync((void**)&r->dev, two, srv->copy);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(r->dev, r->host_in.data(), r->bytes, hipMemcpyHostToDevice, srv->copy);
+      e = hipMemcpyAsync(r->dev, r->host_in, r->bytes, hipMemcpyHostToDevice, srv->copy);
     if (e != hipSuccess) {
       if (r->dev) (void)hipFreeAsync(r->dev, srv->copy);
       r->dev = nullptr;
@@ -222,6 +263,10 @@ void scheduler(stencil_server_s* srv) {
     }
     for (size_t k = 0; k < round.size(); ++k) {
       Request* r = round[k];
+      if (r->host_in) {  // its input copy finished before this round started
+        srv->pinned.put(r->host_in, r->host_cls);
+        r->host_in = nullptr;
+      }
       if (st != STENCIL_OK || js[k] != STENCIL_OK) {
         finish_locked(srv, r, RState::kFailed, st != STENCIL_OK ? st : js[k]);
         continue;
@@ -243,6 +288,12 @@ void release_locked(stencil_server_s* srv, Request* r) {
   }
   if (r->dev) (void)hipFreeAsync(r->dev, srv->collect);
   r->dev = nullptr;
+  if (r->host_in) {
+    // the admission copy may still be in flight for a request that never ran
+    (void)hipStreamSynchronize(srv->copy);
+    srv->pinned.put(r->host_in, r->host_cls);
+    r->host_in = nullptr;
+  }
   srv->cv_work.notify_all();  // a slot and memory are free again
 }
 
@@ -270,9 +321,18 @@ stencil_status collect(stencil_server_s* srv, uint64_t ticket, void* host_out, b
     lock.unlock();
     hipError_t e;
     {
+      // device -> pinned bounce block by DMA, then a host copy
       std::lock_guard<std::mutex> cl(srv->collect_mu);
-      e = hipMemcpyAsync(host_out, src, bytes, hipMemcpyDeviceToHost, srv->collect);
-      if (e == hipSuccess) e = hipStreamSynchronize(srv->collect);
+      size_t cls = 0;
+      void* bounce = srv->pinned.get(bytes, &cls);
+      if (!bounce) {
+        e = hipErrorOutOfMemory;
+      } else {
+        e = hipMemcpyAsync(bounce, src, bytes, hipMemcpyDeviceToHost, srv->collect);
+        if (e == hipSuccess) e = hipStreamSynchronize(srv->collect);
+        if (e == hipSuccess) std::memcpy(host_out, bounce, bytes);
+        srv->pinned.put(bounce, cls);
+      }
     }
     lock.lock();
     if (e != hipSuccess) st = hip_fail(e, "server result copy");
@@ -361,8 +421,9 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
   r->job.in = nullptr;
   r->job.out = nullptr;
   r->job.depth = 0;
-  r->host_in.resize(r->bytes);
-  std::memcpy(r->host_in.data(), host_in, r->bytes);
+  r->host_in = srv->pinned.get(r->bytes, &r->host_cls);
+  if (!r->host_in) return fail(STENCIL_ERR_NOMEM, "pinned staging of %zu bytes failed", r->bytes);
+  std::memcpy(r->host_in, host_in, r->bytes);
   std::lock_guard<std::mutex> lock(srv->mu);
   r->ticket = srv->next_ticket++;
   r->t_submit = Clock::now();
@@ -427,8 +488,11 @@ stencil_status stencil_server_destroy(stencil_server_t srv) {
   (void)hipSetDevice(srv->cfg.device);
   if (srv->compute) (void)hipStreamSynchronize(srv->compute);
   if (srv->copy) (void)hipStreamSynchronize(srv->copy);
-  for (auto& kv : srv->all)
+  for (auto& kv : srv->all) {
     if (kv.second->dev) (void)hipFreeAsync(kv.second->dev, srv->collect);
+    srv->pinned.put(kv.second->host_in, kv.second->host_cls);  // freed with the pool
+    kv.second->host_in = nullptr;
+  }
   if (srv->collect) (void)hipStreamSynchronize(srv->collect);
   if (srv->round_end) (void)hipEventDestroy(srv->round_end);
   if (srv->inputs_ready) (void)hipEventDestroy(srv->inputs_ready);
