@@ -243,12 +243,17 @@ __device__ __forceinline__ void plane_step(State<Real, R, DEPTH, Z0, BY>& st, co
     // buffers they alternate with the running level count (even per unrolled
     // block), so one barrier per level separates every write from the last
     // read of the same buffer.
+    // a star tap off the plane row has dx = 0, so only the lane's own columns
+    // of the rows above and below are needed; other patterns also read the
+    // corners (the x-extended columns)
+    constexpr int kQa = SHAPE == kStar ? R : 0;
+    constexpr int kQb = SHAPE == kStar ? R + BX : XL::kRowW;
     Real* xb = xchg + (XL::kBufs == 2 ? ((ph * t.d + s) & 1) * XL::kPerBuf : 0);
     {
 #pragma unroll
       for (int c = 0; c < R; ++c)
 #pragma unroll
-        for (int q = 0; q < XL::kRowW; ++q) {
+        for (int q = kQa; q < kQb; ++q) {
           xb[(c * XL::kRowW + q) * kThreads + lane_id_t] = ext[R + c][q];            // top rows
           xb[((R + c) * XL::kRowW + q) * kThreads + lane_id_t] = ext[BY + c][q];     // bottom rows
         }
@@ -268,7 +273,7 @@ __device__ __forceinline__ void plane_step(State<Real, R, DEPTH, Z0, BY>& st, co
 #pragma unroll
       for (int c = 0; c < R; ++c)
 #pragma unroll
-        for (int q = 0; q < XL::kRowW; ++q) {
+        for (int q = kQa; q < kQb; ++q) {
           ext[c][q] = above[c * a_c + q * a_q];
           ext[R + BY + c][q] = below[c * b_c + q * b_q];
         }
