@@ -232,6 +232,60 @@ def bench_autotune(torch, np, stencil, problems, xs, ys):
     return {"workload": "2D single-grid suite, plans from the autotuner's cache", "per_stencil": rows}
 
 
+def bench_naive(torch, np, stencil, problems, xs, ys, T=20):
+    """GCells/s of the plain one-step-per-launch kernel (t = 1) on the suite."""
+    rows = []
+    for prob, x, y in zip(problems, xs, ys):
+        plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, T,
+                            flags=stencil.STENCIL_FLAG_NAIVE)
+        plan.execute(x, y)
+        t = timed(torch, lambda: plan.execute(x, y))
+        rows.append({"stencil": prob.spec.name, "T": T, "gcells_per_s": round(prob.cells * T / t / 1e9, 1)})
+        plan.close()
+    return rows
+
+
+def bench_small_jacobi(torch, np, stencil, workloads, reps=20):
+    """The small Jacobi workload (256^2 interior, T = 16, FP64): latency of one
+    stencil_execute (launch-bound) and of stencil_run (planning included)."""
+    prob = workloads.small_jacobi_problem()
+    x = torch.from_numpy(prob.field(np.float64)).cuda()
+    y = torch.empty_like(x)
+    plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, prob.T)
+    plan.execute(x, y)
+    lat = sorted(timed(torch, lambda: plan.execute(x, y)) for _ in range(reps))
+    stream = torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+    wall = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        stencil.stencil_run(prob.coeffs, prob.spec.r, prob.interior, np.float64, prob.T, x.data_ptr(),
+                            y.data_ptr(), stream)
+        torch.cuda.synchronize()
+        wall.append(time.perf_counter() - t0)
+    wall.sort()
+    out = {"workload": "2D 5-point Jacobi, weights 0.2, 256x256 FP64 interior, T=16",
+           "scheme": plan.info["scheme_name"], "depth": plan.info["depth"],
+           "execute_us_median": round(lat[len(lat) // 2] * 1e6, 1), "execute_us_best": round(lat[0] * 1e6, 1),
+           "run_wall_us_median": round(wall[len(wall) // 2] * 1e6, 1)}
+    plan.close()
+    return out
+
+
+def batch_bound_seconds(np, stencil, probs, dtype, B):
+    """max(sum of algorithmic bytes / B, sum of flops / F) for a batch."""
+    S = 8 if dtype == np.float64 else 4
+    F = (FP64_VALU_TFLOPS if dtype == np.float64 else FP32_VALU_TFLOPS) * 1e12
+    nbytes = 0.0
+    nflops = 0.0
+    for p in probs:
+        plan = stencil.Plan(p.coeffs, p.spec.r, p.interior, dtype, p.T)
+        nbytes += 2.0 * S * p.cells * plan.info["passes"]
+        plan.close()
+        nflops += 2.0 * p.spec.points * p.updates
+    return max(nbytes / (B * 1e9), nflops / F), nbytes, nflops
+
+
 def bench_batch(torch, np, stencil, workloads):
     """128 heterogeneous grids, one batched submission per dtype."""
     probs = workloads.batch_problems()
@@ -246,7 +300,10 @@ def bench_batch(torch, np, stencil, workloads):
         stencil.stencil_sync()
         t = timed(torch, lambda: stencil.run_batch(probs, xs, ys))
         stencil.stencil_sync()
-        out[name] = {"s": round(t, 4), "gcells_per_s": round(upd / t / 1e9, 1)}
+        bound, nbytes, nflops = batch_bound_seconds(np, stencil, probs, dt, bench_batch.B)
+        out[name] = {"s": round(t, 4), "gcells_per_s": round(upd / t / 1e9, 1),
+                     "bound_s": round(bound, 4), "fraction_of_bound": round(bound / t, 4),
+                     "algorithmic_GB": round(nbytes / 1e9, 2), "tflop": round(nflops / 1e12, 2)}
         log(f"  batch {name}: {out[name]}")
         ys_by[name] = ys
         del xs
@@ -260,22 +317,36 @@ def bench_batch(torch, np, stencil, workloads):
     return out
 
 
-def bench_serving(np, torch, stencil, workloads, seconds=3.0, rate=200.0):
-    """Serving loop under open-loop Poisson arrivals, FP32, 200 GB budget."""
+def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmup=200):
+    """Serving loop under open-loop Poisson arrivals, FP32, 200 GB budget:
+    `warmup` requests, then the measured ones (seconds * rate); latency from
+    submit to the end of the round that completes the request (H2D included).
+    Also: FP32 error against the FP64 path on a seeded 5% sample plus the 10
+    largest requests, FP64 plain throughput (one plan at a time) on the first
+    200 measured requests, and a stress run with a 0.5 GB budget at 2x rate."""
     from paper_2305_07390_amd import serving
-    count = max(1, int(seconds * rate))
+    measured = max(1, int(seconds * rate))
+    count = warmup + measured
     reqs, arr = workloads.serving_requests(count, rate_hz=rate, dtype=np.float32)
-    offered = sum(p.cells * T for p, _, T in reqs) / max(float(arr[-1]), 1e-9)
-    # FP32 error against the FP64 path for the first few requests
-    sample = {}
+    span = float(arr[-1] - arr[warmup]) if measured > 1 else 1.0
+    offered = sum(p.cells * T for p, _, T in reqs[warmup:]) / max(span, 1e-9)
+    rng = np.random.default_rng(6)
+    sizes = [p.cells * T for p, _, T in reqs]
+    sample = set(int(k) for k in rng.choice(np.arange(warmup, count), size=max(1, measured // 20),
+                                            replace=False))
+    sample |= set(int(k) for k in np.argsort(sizes)[-10:])
+    kept = {}
+
     def keep(k, res):
-        if k < 8:
-            sample[k] = res
+        if k in sample:
+            kept[k] = res
     with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=64) as srv:
         res = serving.serve_open_loop(srv, reqs, arr, on_result=keep)
+    lat = np.array(res["latency_s"][warmup:]) if len(res["latency_s"]) > warmup else np.array(res["latency_s"])
     s = res["stats"]
+    # FP32 error against the FP64 path (bit-identical to the oracle in the parity tests)
     err = 0.0
-    for k, got in sample.items():
+    for k, got in kept.items():
         prob, field, T = reqs[k]
         x = torch.from_numpy(field.astype(np.float64)).cuda()
         y = torch.empty_like(x)
@@ -285,17 +356,42 @@ def bench_serving(np, torch, stencil, workloads, seconds=3.0, rate=200.0):
         ref = y.cpu().numpy()
         plan.close()
         err = max(err, float(np.max(np.abs(got.astype(np.float64) - ref))) / float(np.max(np.abs(ref))))
-    out = {"workload": f"Poisson arrivals {rate:g} req/s for {seconds:g} s, grids drawn like the "
-                       "batch (pool of 32), FP32, 200 GB HBM budget",
+    # FP64 plain on the same requests, one plan at a time
+    sub = reqs[warmup:warmup + 200]
+    t64 = 0.0
+    u64 = 0
+    for prob, field, T in sub:
+        x = torch.from_numpy(field.astype(np.float64)).cuda()
+        y = torch.empty_like(x)
+        plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, T)
+        plan.execute(x, y)
+        t64 += timed(torch, lambda: plan.execute(x, y))
+        u64 += prob.cells * T
+        plan.close()
+    # stress: small budget, twice the rate, so admission binds
+    sreqs, sarr = workloads.serving_requests(400, rate_hz=2 * rate, seed=9, dtype=np.float32)
+    with serving.Server(hbm_budget_bytes=5 * 10**8, max_slots=64) as srv:
+        sres = serving.serve_open_loop(srv, sreqs, sarr)
+    ss = sres["stats"]
+    slat = np.array(sres["latency_s"])
+    out = {"workload": f"Poisson arrivals {rate:g} req/s, {warmup} warm-up + {measured} measured requests, "
+                       "grids drawn like the batch (pool of 32), FP32, 200 GB HBM budget",
            "requests": count, "completed": s["completed"], "rejected": len(res["rejected"]),
            "offered_gcells_per_s": round(offered / 1e9, 1),
            "throughput_gcells_per_s": round(s["cell_updates"] / max(s["wall_s"], 1e-9) / 1e9, 1),
-           "p50_ms": round(s["p50_s"] * 1e3, 2), "p99_ms": round(s["p99_s"] * 1e3, 2),
-           "mean_ms": round(s["mean_s"] * 1e3, 2), "rounds": s["rounds"],
+           "throughput_req_per_s": round(s["completed"] / max(s["wall_s"], 1e-9), 1),
+           "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+           "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+           "mean_ms": round(float(lat.mean()) * 1e3, 2), "rounds": s["rounds"],
            "max_active": s["max_active"], "hbm_peak_GB": round(s["hbm_peak"] / 1e9, 2),
-           "device_busy_frac": round(s["busy_s"] / max(s["wall_s"], 1e-9), 3),
-           "submit_lag_ms": round(res["submit_lag_s"] * 1e3, 2),
-           "f32_max_err_rel_to_max_sample8": err}
+           "submit_lag_ms": round(float(res["submit_lag_s"]) * 1e3, 2),
+           "f32_max_err_rel_to_max": err, "f32_err_sample": len(kept),
+           "fp64_plain_gcells_per_s_first200": round(u64 / max(t64, 1e-9) / 1e9, 1),
+           "stress": {"budget_GB": 0.5, "rate": 2 * rate, "requests": 400, "completed": ss["completed"],
+                      "rejected": len(sres["rejected"]), "max_active": ss["max_active"],
+                      "hbm_peak_GB": round(ss["hbm_peak"] / 1e9, 2),
+                      "p50_ms": round(float(np.percentile(slat, 50)) * 1e3, 2),
+                      "p99_ms": round(float(np.percentile(slat, 99)) * 1e3, 2)}}
     log(f"  serving: {out}")
     return out
 
@@ -310,7 +406,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 3D suite, batch and serving measurements")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--depth", type=int, default=0, help="force a temporal depth (0 = plan)")
     ap.add_argument("--probe", action="store_true",
                     help="run the short program used for PMC counter passes and exit")
@@ -361,7 +457,7 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    per = [[0.0, 0] for _ in problems]
+    per = [[0.0, 0, []] for _ in problems]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -372,6 +468,7 @@ def main():
         for j, (a, b) in enumerate(ev):
             per[j][0] += a.elapsed_time(b) * 1e-3
             per[j][1] += 1
+            per[j][2].append(a.elapsed_time(b) * 1e-3)
         log(f"  step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -381,8 +478,9 @@ def main():
     S = 8
     breakdown = []
     dominant = None
-    for prob, plan, (tsum, cnt) in zip(problems, plans, per):
+    for prob, plan, (tsum, cnt, ts) in zip(problems, plans, per):
         t = tsum / cnt
+        ts = sorted(ts)
         info = plan.info
         t_eff = prob.T / info["passes"]
         gcells = prob.updates / t / 1e9
@@ -397,6 +495,8 @@ def main():
             "passes": info["passes"], "t_eff": round(t_eff, 3), "scheme": info["scheme_name"],
             "tiles": info["tiles"], "seg_len": info["seg_len"], "ms": round(t * 1e3, 3),
             "gcells_per_s": round(gcells, 2),
+            "gcells_best": round(prob.updates / ts[0] / 1e9, 2),
+            "gcells_median": round(prob.updates / ts[len(ts) // 2] / 1e9, 2),
             "roofline_gcells": round(min(r_hbm, r_valu), 1),
             "fraction": round(gcells / min(r_hbm, r_valu), 4),
             "fraction_spec_hbm": round(gcells / min(r_hbm_spec, r_valu), 4),
@@ -450,6 +550,12 @@ def main():
         "per_stencil": breakdown,
     }
     if not args.no_extras:
+        log("2D suite, plain t=1 kernel ...")
+        naive = bench_naive(torch, np, stencil, problems, xs, ys)
+        for row, nv in zip(breakdown, naive):
+            row["naive_t1_gcells_per_s"] = nv["gcells_per_s"]
+        log("grid sync probe ...")
+        result["grid_sync_us"] = round(stencil.stencil_probe_grid_sync(2000) * 1e6, 3)
         log("2D suite, persistent launches ...")
         result["suite_2d_persistent"] = bench_persistent(torch, np, stencil, problems, xs, ys)
         log("2D suite, autotuned ...")
@@ -457,9 +563,12 @@ def main():
     del xs, ys
     torch.cuda.empty_cache()
     if not args.no_extras:
+        log("small Jacobi ...")
+        result["small_jacobi"] = bench_small_jacobi(torch, np, stencil, workloads)
         log("3D suite ...")
         result["suite_3d"] = bench_3d(torch, np, stencil, workloads)
         log("batch ...")
+        bench_batch.B = B
         result["batch"] = bench_batch(torch, np, stencil, workloads)
         log("serving ...")
         result["serving"] = bench_serving(np, torch, stencil, workloads, seconds=args.serve_seconds)

@@ -178,6 +178,15 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
  * error, else STENCIL_OK. */
 stencil_status stencil_sync(void* stream);
 
+/* Diagnostic: average time of one device-wide synchronisation of a grid of
+ * one workgroup per CU through a counter in device memory (the mechanism
+ * that separates passes in persistent launches; the paper's T_Dsync, Section
+ * 5.2.2), over `rounds` barriers in one launch after a warm-up launch.
+ * Synchronises `stream`. Errors: STENCIL_ERR_INVALID (rounds < 1, NULL
+ * result, rounds above 1e6), STENCIL_ERR_TIMEOUT (a bounded wait expired),
+ * device errors. */
+stencil_status stencil_probe_grid_sync(int32_t rounds, void* stream, double* seconds_per_sync);
+
 /* ---- Practical attainable performance model (paper Section 5, Section 6) ----
  *
  * Times of the three pressure points for one tile step of depth t:

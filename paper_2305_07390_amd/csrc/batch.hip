@@ -42,6 +42,37 @@ size_t batch_lds_3d(int dtype, int r, int shape) {
 
 namespace {
 
+// Grid-wide synchronisation probe: `rounds` device-wide barriers of the whole
+// grid (one workgroup per CU) through one counter in device memory, the
+// mechanism that separates passes in the persistent launches. Every wait is
+// bounded by the realtime-clock watchdog; an expired wait sets *err and the
+// workgroup leaves.
+__global__ __launch_bounds__(64) void grid_sync_probe_kernel(unsigned int* ctr, unsigned int* err,
+                                                             int rounds, long long timeout_ticks) {
+  const int lane = (int)threadIdx.x;
+  const unsigned g = gridDim.x;
+  for (int k = 0; k < rounds; ++k) {
+    __hip_atomic_fetch_add(ctr, lane == 0 ? 1u : 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned need = (unsigned)(k + 1) * g;
+    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+    bool ok = true;
+    while (true) {
+      const unsigned v = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+      if (v >= need) break;
+      if ((long long)__builtin_amdgcn_s_memrealtime() - t0 > timeout_ticks) {
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (!ok) {
+      __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+  }
+}
+
 // blockIdx.y = job, blockIdx.x strides over the padded rows (z, y) of that job.
 template <typename Real>
 __global__ __launch_bounds__(64) void frame_copy_batch_kernel(const FrameCopyJob* __restrict__ jobs) {
@@ -67,6 +98,13 @@ __global__ __launch_bounds__(64) void frame_copy_batch_kernel(const FrameCopyJob
 }
 
 }  // namespace
+
+hipError_t grid_sync_probe_launch(unsigned int* ctr, unsigned int* err, int rounds, int grid,
+                                  long long timeout_ticks, hipStream_t stream) {
+  hipLaunchKernelGGL(grid_sync_probe_kernel, dim3(grid), dim3(64), 0, stream, ctr, err, rounds,
+                     timeout_ticks);
+  return hipGetLastError();
+}
 
 hipError_t frame_copy_batch_launch(int dtype, const FrameCopyJob* jobs_dev, int njobs,
                                    hipStream_t stream) {

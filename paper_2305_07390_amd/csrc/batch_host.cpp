@@ -492,6 +492,41 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
   return st;
 }
 
+stencil_status stencil_probe_grid_sync(int32_t rounds, void* stream, double* seconds_per_sync) {
+  if (!seconds_per_sync || rounds < 1 || rounds > 1000000)
+    return fail(STENCIL_ERR_INVALID, "rounds in [1, 1e6] and a result pointer");
+  *seconds_per_sync = 0;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned int* err = device_error_word();
+  if (!err) return fail(STENCIL_ERR_NOMEM, "device error word allocation failed");
+  DeviceInfo di = device_info();
+  if (!di.ok) return fail(STENCIL_ERR_DEVICE, "no device");
+  unsigned int* ctr = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ctr, 256, s);
+  if (e != hipSuccess) return hip_fail(e, "probe counter");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  stencil_status st = STENCIL_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(STENCIL_ERR_DEVICE, "events");
+  // one launch to warm up, then the timed one
+  for (int rep = 0; rep < 2 && st == STENCIL_OK; ++rep) {
+    e = hipMemsetAsync(ctr, 0, sizeof(unsigned int), s);
+    if (e == hipSuccess && rep == 1) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = grid_sync_probe_launch(ctr, err, rounds, di.cus, kTimeoutTicks, s);
+    if (e == hipSuccess && rep == 1) e = hipEventRecord(e1, s);
+    if (e != hipSuccess) st = hip_fail(e, "grid sync probe");
+  }
+  if (st == STENCIL_OK) st = stencil_sync(stream);
+  if (st == STENCIL_OK) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *seconds_per_sync = ms * 1e-3 / rounds;
+  }
+  (void)hipFreeAsync(ctr, s);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return st;
+}
+
 stencil_status stencil_sync(void* stream) {
   hipStream_t s = (hipStream_t)stream;
   unsigned int* err = device_error_word();

@@ -105,6 +105,9 @@ hipError_t batch_launch(int dtype, const void* params, int grid, size_t lds_byte
 // 3D variant needs.
 int batch_max_depth(int dtype, int ndim, int r, int shape);
 size_t batch_lds_3d(int dtype, int r, int shape);
+// Device-wide barrier probe (one workgroup per CU), see stencil_probe_grid_sync.
+hipError_t grid_sync_probe_launch(unsigned int* ctr, unsigned int* err, int rounds, int grid,
+                                  long long timeout_ticks, hipStream_t stream);
 hipError_t frame_copy_batch_launch(int dtype, const FrameCopyJob* jobs_dev, int njobs,
                                    hipStream_t stream);
 

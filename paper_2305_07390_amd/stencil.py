@@ -148,6 +148,7 @@ _SIGNATURES = {
     "stencil_batch_submit": (ctypes.c_int, [ctypes.POINTER(stencil_job), ctypes.c_int32, _P,
                                              ctypes.POINTER(ctypes.c_int)]),
     "stencil_sync": (ctypes.c_int, [_P]),
+    "stencil_probe_grid_sync": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
     "stencil_model_eval": (ctypes.c_int, [ctypes.POINTER(stencil_model_params),
                                            ctypes.POINTER(stencil_model_result)]),
     "stencil_tune": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape), ctypes.c_int,
@@ -294,6 +295,13 @@ def stencil_batch_submit(specs, stream: int = 0):
     st = (ctypes.c_int * n)()
     _check(lib.stencil_batch_submit(arr, n, stream or None, st))
     return list(st)
+
+
+def stencil_probe_grid_sync(rounds: int = 1000, stream: int = 0) -> float:
+    """Seconds per device-wide synchronisation (one workgroup per CU)."""
+    out = ctypes.c_double()
+    _check(load_library().stencil_probe_grid_sync(int(rounds), stream or None, ctypes.byref(out)))
+    return out.value
 
 
 def stencil_sync(stream: int = 0):

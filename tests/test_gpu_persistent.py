@@ -30,3 +30,13 @@ def test_persistent_equals_oracle(name, interior, T, dtype):
                           return_info=True)
     assert info["passes"] >= 2, info
     np.testing.assert_array_equal(got, ref)
+
+
+def test_grid_sync_probe():
+    """One grid-wide barrier of one workgroup per CU costs microseconds, not
+    milliseconds, and the probe leaves no device error behind."""
+    t = st.stencil_probe_grid_sync(500)
+    assert 0 < t < 1e-4, t
+    st.stencil_sync()
+    with pytest.raises(st.StencilError):
+        st.stencil_probe_grid_sync(0)
