@@ -72,7 +72,13 @@ typedef struct {
  *        persistent launch (one workgroup per CU), each pass starting once the
  *        grid-wide count of finished tiles of the previous pass is complete (the
  *        inter-pass grid synchronisation of paper Section 2.1.3, bounded by a
- *        watchdog that stencil_sync reports); ignored for other schemes. */
+ *        watchdog that stencil_sync reports); ignored for other schemes;
+ *        STENCIL_FLAG_UNIFORM_TILES keeps the two edge strips of a blocked 2D
+ *        plan at the interior segment length. By default their tiles, which
+ *        also apply the Dirichlet columns and so cost more per row, are cut
+ *        into shorter segments that take the wave slots the interior tiles
+ *        leave free, so that no pass waits on them (batches set this flag:
+ *        their jobs share the slots). */
 typedef struct {
   int32_t tile[3];
   int32_t depth;
@@ -82,6 +88,7 @@ typedef struct {
 #define STENCIL_FLAG_NAIVE 1
 #define STENCIL_FLAG_NO_CACHE 2
 #define STENCIL_FLAG_PERSISTENT 4
+#define STENCIL_FLAG_UNIFORM_TILES 8
 
 /* Execution scheme chosen by a plan. */
 typedef enum {
@@ -110,6 +117,9 @@ typedef struct {
   int64_t cells;         /* interior cells */
   int64_t padded_bytes;  /* bytes of one padded array */
   int64_t workspace_bytes;
+  int32_t edge_seg_len;  /* rows per segment of the two edge strips (2D) */
+  int32_t edge_tiles;    /* tiles of the edge strips when they have their own
+                            segments (2D), else 0 */
 } stencil_plan_info;
 
 typedef struct stencil_plan_s* stencil_plan_t;

@@ -176,6 +176,8 @@ BatchJob<Real> make_job(const stencil_plan_s* p, const void* in, void* out, void
   if (p->ndim == 2) {
     J.strips = p->strips;
     J.hl = p->hl;
+    J.seg_len_e = p->seg_len_e;
+    J.edge_tiles = p->edge_tiles;
   } else {
     J.sx = p->sx;
     J.sy = p->sy;
@@ -413,6 +415,7 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     std::memset(&hint, 0, sizeof(hint));
     hint.depth = j.depth;
     hint.tile[0] = j.shape.ndim == 2 ? kBatchSeg2D : kBatchSeg3D;
+    hint.flags = STENCIL_FLAG_UNIFORM_TILES;  // the jobs share the wave slots
     stencil_plan_t pl = nullptr;
     status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
     int tuned_depth = 0, tuned_seg = 0;
@@ -441,6 +444,7 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
         stencil_plan_destroy(pl);
         pl = nullptr;
         hint.tile[0] = 0;
+        hint.flags = 0;
         status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
       }
     }

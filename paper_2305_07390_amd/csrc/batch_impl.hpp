@@ -96,8 +96,7 @@ template <typename Real, int R, int SHAPE>
 __device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int tile, Real* hq, int lane) {
   constexpr int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 2, R, SHAPE);
   if constexpr (DEPTH > 0) {
-    constexpr int V = ColsPerLane<Real>::value;
-    constexpr int W = kWave * V;
+    constexpr int V = tb2d_cols(sizeof(Real) == 8, R, SHAPE);
     constexpr int KB = (2 * R + 1) * (2 * R + 1);
     Real wl[KB];
 #pragma unroll
@@ -109,30 +108,21 @@ __device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int ti
     pass_buffers(in, uni_ptr(J.out), uni_ptr(J.ws), npass, pass, &src, &dst);
     const int d = pass == npass - 1 ? uni(J.depth_last) : uni(J.depth);
     const int P = (int)uni(J.P), Q = (int)uni(J.Qy);
-    const int ns = uni(J.strips), HL = uni(J.hl), seg_len = uni(J.seg_len);
-    const int seg = tile / ns;
-    const int strip = tile - seg * ns;
-    const int Y0 = seg * seg_len;
-    const int Y1 = (Y0 + seg_len < Q) ? Y0 + seg_len : Q;
-    int edge, X0, la, lb;
-    if (ns == 1) {
-      edge = kBothEdges; X0 = R; la = 0; lb = kWave;
-    } else if (strip == 0) {
-      edge = kLeftEdge; X0 = R; la = 0; lb = kWave - HL;
-    } else if (strip == ns - 1) {
-      edge = kRightEdge; X0 = P - R - W; la = HL; lb = kWave;
-    } else {
-      edge = kInterior;
-      X0 = R + (kWave - HL) * V + (strip - 1) * (kWave - 2 * HL) * V - HL * V;
-      la = HL; lb = kWave - HL;
-    }
+    const int ns = uni(J.strips), HL = uni(J.hl);
+    const Tile2D g = locate_2d(tile, ns, uni(J.seg_len), uni(J.seg_len_e), uni(J.edge_tiles), P, Q,
+                               R, V, HL);
+    const int edge = g.edge, X0 = g.X0, la = g.la, lb = g.lb, Y0 = g.Y0, Y1 = g.Y1;
     // Full-depth passes (all but a job's last) get the depth as a constant,
     // so the level loop unrolls without per-level checks, as in the
-    // single-grid kernel; the remainder pass takes it at run time.
+    // single-grid kernel; the remainder pass takes it at run time. One tile
+    // body serves interior and edge strips here (the fused kernel's register
+    // budget has no room for a second copy).
     if (d == DEPTH)
-      tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0, Y1, DEPTH);
+      tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb,
+                                                     Y0, Y1, DEPTH);
     else
-      tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0, Y1, d);
+      tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb,
+                                                     Y0, Y1, d);
   }
 }
 

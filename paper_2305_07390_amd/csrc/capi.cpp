@@ -98,8 +98,8 @@ int default_depth_2d(int r, int pattern, int dtype) {
   return std::min(d, maxd);
 }
 
-void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
-  const int V = tb2d_cols_per_lane(p->dtype);
+void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus, bool edge_split) {
+  const int V = tb2d_cols_per_lane(p->dtype, p->r, p->pattern);
   const int W = kWave * V;
   const int HL = (depth * p->r + V - 1) / V;
   const int64_t nx = p->n[2];
@@ -136,6 +136,28 @@ void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
   p->seg_len = seg;
   p->segs = (int)((Q + seg - 1) / seg);
   p->tiles = p->strips * p->segs;
+  p->seg_len_e = seg;
+  p->edge_tiles = 0;
+  if (edge_split && p->strips > 2) {
+    // Edge-strip tiles also apply the Dirichlet columns and cost more per
+    // row; a pass whose tiles all run at once ends with its slowest tile.
+    // Cut the two edge strips into shorter segments that take the wave slots
+    // the interior tiles leave free (down to two thirds of the interior
+    // length, which covers the measured extra cost).
+    const int64_t slots = (int64_t)cus * 4;
+    const int64_t spare = slots - (int64_t)(p->strips - 2) * p->segs;
+    if (spare / 2 > p->segs) {
+      int64_t se = (Q + spare / 2 - 1) / (spare / 2);
+      se = std::max<int64_t>(se, (2 * (int64_t)seg + 2) / 3);
+      se = std::max<int64_t>(se, std::min<int64_t>(seg, std::max(16, 4 * depth * p->r)));
+      const int64_t segs_e = (Q + se - 1) / se;
+      if (se < seg && segs_e > p->segs) {
+        p->seg_len_e = (int)se;
+        p->edge_tiles = (int)(2 * segs_e);
+        p->tiles = p->edge_tiles + (p->strips - 2) * p->segs;
+      }
+    }
+  }
   p->hq_rows = seg + 2 * depth * p->r + 8;
   p->block = 256;
   p->grid = (p->tiles + 3) / 4;
@@ -251,6 +273,8 @@ stencil_status run_blocked_2d(const stencil_plan_s* p, const void* in, void* out
   prm.ntiles = p->tiles;
   prm.hq_rows = p->hq_rows;
   prm.hl = p->hl;
+  prm.seg_len_e = p->seg_len_e;
+  prm.edge_tiles = p->edge_tiles;
   for (size_t i = 0; i < p->coeffs.size(); ++i) prm.w[i] = (Real)p->coeffs[i];
   const size_t lds = (size_t)4 * p->hq_rows * 2 * p->r * sizeof(Real);
   const void* src = in;
@@ -416,7 +440,7 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
     p->scheme = STENCIL_SCHEME_NAIVE;
     p->depth = 1;
     if (!force_naive && p->ndim == 2 && radius >= 1 && p->points > 0) {
-      const int V = tb2d_cols_per_lane(dtype);
+      const int V = tb2d_cols_per_lane(dtype, radius, p->pattern);
       const int maxd = tb2d_max_depth(dtype, radius, p->pattern);
       int depth = (hint && hint->depth > 0) ? hint->depth : default_depth_2d(radius, p->pattern, dtype);
       if (depth > maxd) depth = maxd;
@@ -428,7 +452,8 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
         const int cus = di.ok ? di.cus : 256;
         p->scheme = STENCIL_SCHEME_BLOCKED_2D;
         p->depth = depth;
-        plan_2d_tiles(p, depth, hint ? hint->tile[0] : 0, cus);
+        plan_2d_tiles(p, depth, hint ? hint->tile[0] : 0, cus,
+                      !(hint && (hint->flags & STENCIL_FLAG_UNIFORM_TILES)));
       }
     }
     if (!force_naive && p->ndim == 3 && radius >= 1 && p->points > 0) {
@@ -459,7 +484,8 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
           DeviceInfo di = device_info();
           const int cus = di.ok ? di.cus : 256;
           p->depth = cap;
-          if (p->scheme == STENCIL_SCHEME_BLOCKED_2D) plan_2d_tiles(p, cap, hint->tile[0], cus);
+          if (p->scheme == STENCIL_SCHEME_BLOCKED_2D)
+            plan_2d_tiles(p, cap, hint->tile[0], cus, !(hint->flags & STENCIL_FLAG_UNIFORM_TILES));
           else plan_3d_tiles(p, cap, hint->tile[0], cus);
         }
       }
@@ -500,7 +526,9 @@ stencil_status stencil_plan_describe(stencil_plan_t plan, stencil_plan_info* inf
   info->tiles = plan->tiles;
   info->strips = plan->strips;
   info->seg_len = plan->seg_len;
-  info->cols_per_lane = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? tb2d_cols_per_lane(plan->dtype)
+  info->edge_seg_len = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? plan->seg_len_e : 0;
+  info->edge_tiles = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? plan->edge_tiles : 0;
+  info->cols_per_lane = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? tb2d_cols_per_lane(plan->dtype, plan->r, plan->pattern)
                         : plan->scheme == STENCIL_SCHEME_BLOCKED_3D ? 4 : 1;
   info->redundant_lanes = plan->scheme == STENCIL_SCHEME_BLOCKED_3D ? plan->hx : plan->hl;
   if (plan->scheme == STENCIL_SCHEME_BLOCKED_3D) info->strips = plan->sx * plan->sy;

@@ -14,14 +14,22 @@ constexpr int kMaxBox2D = (2 * kMaxR + 1) * (2 * kMaxR + 1);
 constexpr int kMaxBox3D = (2 * kMaxR + 1) * (2 * kMaxR + 1) * (2 * kMaxR + 1);
 constexpr int kWave = 64;
 
+// Columns per lane of the blocked 2D kernels: two 16-byte words per lane.
+constexpr int tb2d_cols(bool f64, int r, int shape) {
+  (void)r;
+  (void)shape;
+  return f64 ? 4 : 8;
+}
+
 // One pass of the temporally blocked 2D kernel: DEPTH steps from src to dst.
 // Both arrays are padded (P columns x Q rows, x fastest). The grid is cut into
 // n_strips x n_segs wave tiles (see tb2d.hip for the geometry).
 // `orig` is the operation's original input (its halo is the Dirichlet data).
 // The interior columns r .. P-r-1 are cut into n_strips strips (at least two)
 // laid out with hl redundant lanes on each open side (hl * V >= depth * r for
-// every pass of the plan); rows into n_segs segments of seg_len rows. Each wave
-// keeps hq_rows x 2r halo values in LDS.
+// every pass of the plan); rows into n_segs segments of seg_len rows. With
+// edge_tiles > 0 the two edge strips have their own segments of seg_len_e rows
+// and their tiles come first. Each wave keeps hq_rows x 2r halo values in LDS.
 template <typename Real>
 struct Tb2dParams {
   const void* src;
@@ -29,6 +37,7 @@ struct Tb2dParams {
   const void* orig;
   int64_t P, Q;
   int32_t n_strips, n_segs, seg_len, ntiles, hq_rows, hl;
+  int32_t seg_len_e, edge_tiles;  // edge-strip segments (edge_tiles = 0: none)
   Real w[kMaxBox2D];  // dense (2r+1)^2 coefficient box, dense-box order
 };
 
@@ -81,6 +90,7 @@ struct BatchJob {
   void* ws;
   int64_t P, Qy, Qz;
   int32_t variant, tiles, strips, seg_len, hl, sx, sy, hx, hy, npass, depth, depth_last;
+  int32_t seg_len_e, edge_tiles;
   Real w[125];
 };
 
@@ -133,7 +143,7 @@ hipError_t tb2d_launch(int dtype, int r, int shape, int depth, const void* param
 // Largest depth with a compiled variant (0 if none).
 int tb2d_max_depth(int dtype, int r, int shape);
 // Columns per lane for the given dtype.
-int tb2d_cols_per_lane(int dtype);
+int tb2d_cols_per_lane(int dtype, int r, int shape);
 
 hipError_t naive_launch(int dtype, const void* params, int64_t cells, hipStream_t stream);
 

@@ -49,6 +49,9 @@ struct stencil_plan_s {
   std::vector<int> pass_depth;  // depth of each pass
   // 2D blocked geometry
   int strips = 0, segs = 0, seg_len = 0, tiles = 0, hq_rows = 0, hl = 0;
+  // edge strips with their own (shorter) segments: edge_tiles > 0 lists them
+  // first, two per segment (left, right)
+  int seg_len_e = 0, edge_tiles = 0;
   // 3D blocked geometry
   int sx = 0, sy = 0, hx = 0, hy = 0;
   int grid = 0, block = 0;

@@ -48,6 +48,6 @@ int tb2d_max_depth(int dtype, int r, int shape) {
   return max_depth_c(r, shape);
 }
 
-int tb2d_cols_per_lane(int dtype) { return dtype == kF64 ? 4 : 8; }
+int tb2d_cols_per_lane(int dtype, int r, int shape) { return tb2d_cols(dtype == kF64, r, shape); }
 
 }  // namespace stencil_impl

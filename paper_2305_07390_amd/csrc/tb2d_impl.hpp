@@ -61,10 +61,51 @@ constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
 
 enum Edge { kInterior = 0, kLeftEdge = 1, kRightEdge = 2, kBothEdges = 3 };
 
-template <typename Real>
-struct ColsPerLane {
-  static constexpr int value = 32 / sizeof(Real);  // two 16-byte words per lane
+// Tile `tile` of a pass -> its strip's place in x and its rows [Y0, Y1).
+// Without edge tiles, tile = seg * ns + strip. With edge_tiles > 0 the two
+// edge strips come first, two tiles (left, right) per segment of seg_len_e
+// rows, then the interior strips by segments of seg_len rows.
+struct Tile2D {
+  int edge, X0, la, lb, Y0, Y1;
 };
+
+__device__ __forceinline__ Tile2D locate_2d(int tile, int ns, int seg_len, int seg_len_e,
+                                            int edge_tiles, int P, int Q, int R, int V, int HL) {
+  int strip, Y0, len;
+  if (tile < edge_tiles) {
+    const int seg = tile >> 1;
+    strip = (tile & 1) ? ns - 1 : 0;
+    Y0 = seg * seg_len_e;
+    len = seg_len_e;
+  } else if (edge_tiles > 0) {
+    const int t = tile - edge_tiles, ni = ns - 2;
+    const int seg = t / ni;
+    strip = 1 + (t - seg * ni);
+    Y0 = seg * seg_len;
+    len = seg_len;
+  } else {
+    const int seg = tile / ns;
+    strip = tile - seg * ns;
+    Y0 = seg * seg_len;
+    len = seg_len;
+  }
+  Tile2D g;
+  g.Y0 = Y0;
+  g.Y1 = (Y0 + len < Q) ? Y0 + len : Q;
+  if (ns == 1) {
+    // one strip exactly as wide as the interior: both sides are halo
+    g.edge = kBothEdges; g.X0 = R; g.la = 0; g.lb = kWave;
+  } else if (strip == 0) {
+    g.edge = kLeftEdge; g.X0 = R; g.la = 0; g.lb = kWave - HL;
+  } else if (strip == ns - 1) {
+    g.edge = kRightEdge; g.X0 = P - R - kWave * V; g.la = HL; g.lb = kWave;
+  } else {
+    g.edge = kInterior;
+    g.X0 = R + (kWave - HL) * V + (strip - 1) * (kWave - 2 * HL) * V - HL * V;
+    g.la = HL; g.lb = kWave - HL;
+  }
+  return g;
+}
 
 template <int R>
 struct Ring0 {
@@ -131,6 +172,33 @@ __device__ __forceinline__ void extend_row(const Real (&x)[V], const Real (&el)[
   }
 }
 
+// Interior strips: the first and last HL lanes are redundant, so the lanes
+// without a source lane may take any value (bound_ctrl writes zero) and no
+// halo values are read.
+template <int CTRL>
+__device__ __forceinline__ double dpp_open(double v) {
+  unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, true);
+  int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_open(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf,
+                                                            0xf, true));
+}
+
+template <typename Real, int R, int V>
+__device__ __forceinline__ void extend_row_open(const Real (&x)[V], Real (&xe)[V + 2 * R]) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) xe[R + v] = x[v];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    xe[j] = dpp_open<kDppWaveShr1>(x[V - R + j]);
+    xe[R + V + j] = dpp_open<kDppWaveShl1>(x[j]);
+  }
+}
+
 // Mutable per-tile streaming state (kept in registers after inlining).
 template <typename Real, int R, int DEPTH, int V>
 struct Tb2dState {
@@ -151,7 +219,7 @@ struct Tb2dTile {
 // One streamed row (iteration i, phase ph of the unrolled loop).
 // GENERAL: warm-up/drain rows -- checks which levels hold valid rows and
 // handles the Dirichlet halo rows. Steady rows skip every check.
-template <typename Real, int R, int SHAPE, int DEPTH, int V, bool GENERAL>
+template <typename Real, int R, int SHAPE, int DEPTH, int V, bool EDGE, bool GENERAL>
 __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const Tb2dTile& t,
                                          const Real* __restrict__ w, const Real* hq, const int ph,
                                          const int i) {
@@ -162,6 +230,10 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
     const int ip = i + Z0 - 1;
     if (!GENERAL || ip < t.n_iter)
       load_vec<Real, V>(t.rs, t.col_off + (uint32_t)ip * t.row_bytes, 0, st.L0[(ph + Z0 - 1) % Z0]);
+    // keep the prefetch at the head of its row: the scheduler otherwise sinks
+    // the loads of an unrolled iteration towards its end, and the next
+    // iteration then waits on all of them (vmcnt also counts the stores)
+    if (!GENERAL) __builtin_amdgcn_sched_barrier(0);
   }
   Real x[V];
 #pragma unroll
@@ -174,9 +246,10 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
     if (s > t.d) break;
     const int u = y - (s - 1) * R;  // row of level s-1 arriving now
     const bool ok = !GENERAL || ((u >= t.lo[s - 1]) && (u < Q));
-    // halo values of row u (two copies, so each DPP gets its own register)
-    Real el[R], er[R];
-    {
+    Real xe[V + 2 * R];
+    if constexpr (EDGE) {
+      // halo values of row u (two copies, so each DPP gets its own register)
+      Real el[R], er[R];
       int hrow = u - t.ys;
       if (GENERAL) hrow = hrow < 0 ? 0 : hrow;
 #pragma unroll
@@ -184,9 +257,10 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
         el[j] = hq[hrow * 2 * R + j];
         er[j] = hq[hrow * 2 * R + R + j];
       }
+      extend_row<Real, R, V>(x, el, er, xe);
+    } else {
+      extend_row_open<Real, R, V>(x, xe);
     }
-    Real xe[V + 2 * R];
-    extend_row<Real, R, V>(x, el, er, xe);
 
     // 1) the output completed by this arrival (dy = +r); it was started 2r
     //    arrivals ago in the same slot
@@ -231,9 +305,10 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
   }
 }
 
-// One wave tile of one pass: d (<= DEPTH) levels from src to dst.
-template <typename Real, int R, int SHAPE, int DEPTH, int V>
-__device__ __forceinline__ void tb2d_tile(const Real* __restrict__ w, const void* src, void* dst,
+// One wave tile of one pass: d (<= DEPTH) levels from src to dst. EDGE: the
+// strip touches the left or right side of the grid (edge != kInterior).
+template <typename Real, int R, int SHAPE, int DEPTH, int V, bool EDGE>
+__device__ __forceinline__ void tb2d_tile_impl(const Real* __restrict__ w, const void* src, void* dst,
                                           const void* orig, const int P, const int Q, Real* hq,
                                           const int lane, const int edge, const int X0,
                                           const int la, const int lb, const int Y0, const int Y1,
@@ -270,7 +345,7 @@ __device__ __forceinline__ void tb2d_tile(const Real* __restrict__ w, const void
   // Edge strips: stage the Dirichlet halo columns of the tile's rows in LDS
   // (left strip: columns 0..r-1, right strip: columns P-r..P-1), two copies
   // per row.
-  if (edge != kInterior) {
+  if (EDGE && edge != kInterior) {
     const int rows = (ye < Q - 1 ? ye : Q - 1) - t.ys + 1;
     const __amdgpu_buffer_rsrc_t rin =
         make_rsrc((const char*)orig + (int64_t)t.ys * P * S, (uint32_t)src_range);
@@ -318,23 +393,36 @@ __device__ __forceinline__ void tb2d_tile(const Real* __restrict__ w, const void
   for (; base < i_a; base += UNROLL) {
 #pragma unroll
     for (int ph = 0; ph < UNROLL; ++ph)
-      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, true>(st, t, w, hq, ph, base + ph);
+      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, EDGE, true>(st, t, w, hq, ph, base + ph);
   }
   for (; base < i_b; base += UNROLL) {
 #pragma unroll
-    for (int ph = 0; ph < UNROLL; ++ph) tb2d_row<Real, R, SHAPE, DEPTH, V, false>(st, t, w, hq, ph, base + ph);
+    for (int ph = 0; ph < UNROLL; ++ph) tb2d_row<Real, R, SHAPE, DEPTH, V, EDGE, false>(st, t, w, hq, ph, base + ph);
   }
   for (; base < t.n_iter; base += UNROLL) {
 #pragma unroll
     for (int ph = 0; ph < UNROLL; ++ph)
-      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, true>(st, t, w, hq, ph, base + ph);
+      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, EDGE, true>(st, t, w, hq, ph, base + ph);
   }
+}
+
+template <typename Real, int R, int SHAPE, int DEPTH, int V>
+__device__ __forceinline__ void tb2d_tile(const Real* __restrict__ w, const void* src, void* dst,
+                                          const void* orig, const int P, const int Q, Real* hq,
+                                          const int lane, const int edge, const int X0,
+                                          const int la, const int lb, const int Y0, const int Y1,
+                                          const int d) {
+  if (edge == kInterior)
+    tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, false>(w, src, dst, orig, P, Q, hq, lane, edge, X0, la,
+                                                    lb, Y0, Y1, d);
+  else
+    tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true>(w, src, dst, orig, P, Q, hq, lane, edge, X0, la,
+                                                   lb, Y0, Y1, d);
 }
 
 template <typename Real, int R, int SHAPE, int DEPTH>
 __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
-  constexpr int V = ColsPerLane<Real>::value;
-  constexpr int W = kWave * V;
+  constexpr int V = tb2d_cols(sizeof(Real) == 8, R, SHAPE);
   extern __shared__ char lds_raw[];
   const int lane = lane_id();
   const int waves = blockDim.x / kWave;
@@ -347,25 +435,9 @@ __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
   // strip layout shared by every pass of the plan: hl * V >= DEPTH * r
   const int HL = a.hl;
   for (int tile = blockIdx.x * waves + wid; tile < a.ntiles; tile += stride) {
-    const int seg = tile / ns;
-    const int strip = tile - seg * ns;
-    const int Y0 = seg * a.seg_len;
-    const int Y1 = (Y0 + a.seg_len < Q) ? Y0 + a.seg_len : Q;
-    int edge, X0, la, lb;
-    if (ns == 1) {
-      // one strip exactly as wide as the interior: both sides are halo
-      edge = kBothEdges; X0 = R; la = 0; lb = kWave;
-    } else if (strip == 0) {
-      edge = kLeftEdge; X0 = R; la = 0; lb = kWave - HL;
-    } else if (strip == ns - 1) {
-      edge = kRightEdge; X0 = P - R - W; la = HL; lb = kWave;
-    } else {
-      edge = kInterior;
-      X0 = R + (kWave - HL) * V + (strip - 1) * (kWave - 2 * HL) * V - HL * V;
-      la = HL; lb = kWave - HL;
-    }
-    tb2d_tile<Real, R, SHAPE, DEPTH, V>(a.w, a.src, a.dst, a.orig, P, Q, hq, lane, edge, X0, la,
-                                        lb, Y0, Y1, DEPTH);
+    const Tile2D g = locate_2d(tile, ns, a.seg_len, a.seg_len_e, a.edge_tiles, P, Q, R, V, HL);
+    tb2d_tile<Real, R, SHAPE, DEPTH, V>(a.w, a.src, a.dst, a.orig, P, Q, hq, lane, g.edge, g.X0,
+                                        g.la, g.lb, g.Y0, g.Y1, DEPTH);
   }
 }
 

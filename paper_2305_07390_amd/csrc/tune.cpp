@@ -97,7 +97,7 @@ double model_rate(const stencil_plan_s* pl, int depth, int seg) {
   m.tiling = STENCIL_MODEL_SM_TILING;
   m.rad = pl->r;
   if (pl->ndim == 2) {
-    const int V = f64 ? 4 : 8;
+    const int V = tb2d_cols_per_lane(pl->dtype, pl->r, pl->pattern);
     m.tiled_dims = 2;
     m.tile[0] = 64.0 * V;
     m.tile[1] = seg + 2.0 * depth * pl->r;

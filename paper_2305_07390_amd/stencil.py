@@ -31,6 +31,7 @@ STENCIL_F64 = 1
 STENCIL_FLAG_NAIVE = 1
 STENCIL_FLAG_NO_CACHE = 2
 STENCIL_FLAG_PERSISTENT = 4
+STENCIL_FLAG_UNIFORM_TILES = 8
 
 STENCIL_TUNE_BATCH = 1
 STENCIL_TUNE_FORCE = 2
@@ -73,6 +74,7 @@ class stencil_plan_info(ctypes.Structure):
         ("redundant_lanes", ctypes.c_int32),
         ("grid", ctypes.c_int32), ("block", ctypes.c_int32), ("cells", ctypes.c_int64),
         ("padded_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+        ("edge_seg_len", ctypes.c_int32), ("edge_tiles", ctypes.c_int32),
     ]
 
     def as_dict(self):

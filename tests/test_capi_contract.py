@@ -193,6 +193,54 @@ def test_strip_layout_covers_interior(dtype, r, kind):
             assert covered[r:P - r].all(), (nx, T)
 
 
+def _tile_rows(tile, ns, seg_len, seg_len_e, edge_tiles, Q):
+    """Mirror of the device tile order: (strip, first row, end row)."""
+    if tile < edge_tiles:
+        seg, strip, y0, n = tile // 2, (ns - 1 if tile % 2 else 0), (tile // 2) * seg_len_e, seg_len_e
+    elif edge_tiles > 0:
+        t = tile - edge_tiles
+        seg, strip, y0, n = t // (ns - 2), 1 + t % (ns - 2), (t // (ns - 2)) * seg_len, seg_len
+    else:
+        seg, strip, y0, n = tile // ns, tile % ns, (tile // ns) * seg_len, seg_len
+    return strip, y0, min(y0 + n, Q)
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+@pytest.mark.parametrize("r,kind,interior,seg", [
+    (1, "star", (8192, 8192), 0), (2, "box", (8192, 8192), 0), (3, "star", (8192, 8192), 0),
+    (1, "box", (8192, 8192), 0), (1, "box", (450, 800), 100), (1, "star", (2000, 3000), 0),
+    (2, "star", (600, 1000), 200), (1, "star", (333, 517), 0)])
+def test_edge_strip_segments(dtype, r, kind, interior, seg):
+    """Edge strips get shorter segments only when the interior tiles leave
+    wave slots free; every (strip, row) is covered by exactly one tile either
+    way; STENCIL_FLAG_UNIFORM_TILES turns the split off."""
+    _lib()
+    w = wl.random_coeffs(2, kind, r, 11)
+    T = 1000
+    p = st.Plan(w, r, interior, dtype, T, seg_len=seg)
+    u = st.Plan(w, r, interior, dtype, T, seg_len=seg, flags=st.STENCIL_FLAG_UNIFORM_TILES)
+    for plan in (p, u):
+        i = plan.info
+        assert i["scheme_name"] == "blocked_2d"
+        ns, L, Le, E = i["strips"], i["seg_len"], i["edge_seg_len"], i["edge_tiles"]
+        Q = interior[0] + 2 * r
+        if E:
+            assert ns > 2 and Le < L
+            assert E == 2 * -(-Q // Le) and i["tiles"] == E + (ns - 2) * -(-Q // L)
+            assert i["tiles"] <= 4 * 256
+        else:
+            assert i["tiles"] == ns * -(-Q // L)
+        hits = np.zeros((ns, Q), dtype=np.int32)
+        for t in range(i["tiles"]):
+            strip, y0, y1 = _tile_rows(t, ns, L, Le, E, Q)
+            assert 0 <= strip < ns and 0 <= y0 < y1 <= Q
+            hits[strip, y0:y1] += 1
+        assert (hits == 1).all()
+    assert u.info["edge_tiles"] == 0
+    if seg == 0 and interior == (8192, 8192):
+        assert p.info["edge_tiles"] > 0
+
+
 def test_batch_rejects_shared_outputs_before_device_work():
     _lib()
     w = wl.uniform_5pt_coeffs()

@@ -82,6 +82,23 @@ def test_segment_invariance(seg):
     _check(w, 1, u0, 14, seg_len=seg, depth=7)
 
 
+@pytest.mark.parametrize("kind,r,interior,T,seg", [
+    ("star", 1, (450, 1300), 26, 100), ("box", 1, (611, 1333), 17, 150),
+    ("star", 3, (500, 1200), 9, 120), ("box", 2, (403, 1000), 11, 90),
+    ("star", 2, (700, 1500), 8, 1000)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_edge_strip_segments(kind, r, interior, T, seg, dtype):
+    """Edge strips with their own shorter segments give the oracle's result,
+    the same bits as the uniform tiling."""
+    w = wl.random_coeffs(2, kind, r, 83)
+    u0 = wl.make_field(interior, r, 83, dtype)
+    info = _check(w, r, u0, T, seg_len=seg)
+    assert info["edge_tiles"] > 0 and info["edge_seg_len"] < info["seg_len"], info
+    got = gpu_sweep(w, r, u0, T, seg_len=seg, flags=8)
+    ref = gpu_sweep(w, r, u0, T, seg_len=seg)
+    assert np.array_equal(got, ref)
+
+
 def test_general_pattern():
     w = wl.random_coeffs(2, "box", 1, 79)
     w[0, 2] = 0.0

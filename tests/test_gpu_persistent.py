@@ -32,6 +32,19 @@ def test_persistent_equals_oracle(name, interior, T, dtype):
     np.testing.assert_array_equal(got, ref)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_persistent_edge_segments(dtype):
+    """The persistent kernel follows a plan whose edge strips have their own segments."""
+    spec = {s.name: s for s in wl.ALL_STENCILS}["2d9pt_box_r1"]
+    coeffs = wl.coeffs_for(spec, 63)
+    u0 = wl.make_field((450, 1300), 1, seed=64, dtype=dtype)
+    ref = oracle.sweep(coeffs, 1, u0, 30)
+    got, info = gpu_sweep(coeffs, 1, u0, 30, seg_len=100, flags=st.STENCIL_FLAG_PERSISTENT, repeats=2,
+                          return_info=True)
+    assert info["edge_tiles"] > 0 and info["passes"] >= 2, info
+    np.testing.assert_array_equal(got, ref)
+
+
 def test_grid_sync_probe():
     """One grid-wide barrier of one workgroup per CU costs microseconds, not
     milliseconds, and the probe leaves no device error behind."""
