@@ -82,11 +82,21 @@ def cpu_baseline(problems, fields, budget_s=15.0):
         oracle.sweep(prob.coeffs, prob.spec.r, u0, steps, threads=threads)
         updates += prob.cells * steps
     dt = time.perf_counter() - t0
+    # one thread on the small Jacobi case (256^2 5-point, T = 16)
+    from paper_2305_07390_amd import workloads
+    small = workloads.small_jacobi_problem()
+    su0 = small.field()
+    oracle.sweep(small.coeffs, 1, su0, 1, threads=1)
+    t1 = time.perf_counter()
+    oracle.sweep(small.coeffs, 1, su0, small.T, threads=1)
+    t1 = time.perf_counter() - t1
     return {
         "value": updates / dt / 1e9,
         "unit": "GCells/s",
         "cores": threads,
         "kind": "oracle",
+        "one_thread_small_jacobi": {"gcells_per_s": round(small.updates / t1 / 1e9, 3), "ms": round(t1 * 1e3, 2),
+                                    "workload": "256x256 5-point Jacobi, T=16, FP64, 1 thread"},
         "sample": f"all {len(problems)} stencils of the suite on the full {problems[0].interior[0]}x"
                   f"{problems[0].interior[1]} grid, {steps} steps each ({updates:.3e} updates, "
                   f"{dt:.1f} s)",
@@ -286,6 +296,72 @@ def batch_bound_seconds(np, stencil, probs, dtype, B):
     return max(nbytes / (B * 1e9), nflops / F), nbytes, nflops
 
 
+def bench_paper_benchmarks(torch, np, stencil, workloads):
+    """The paper's nine benchmark stencils at its own domain sizes (FP64; the
+    17- and 19-point 3D sets as defined in workloads), planner defaults."""
+    rows = []
+    for prob in workloads.paper_benchmark_problems():
+        x = torch.from_numpy(prob.field(np.float64)).cuda()
+        y = torch.empty_like(x)
+        plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, prob.T)
+        plan.execute(x, y)
+        t = timed(torch, lambda: plan.execute(x, y))
+        rows.append({"stencil": prob.spec.name, "points": prob.spec.points,
+                     "domain": list(prob.interior[::-1]), "T": prob.T, "scheme": plan.info["scheme_name"],
+                     "depth": plan.info["depth"], "gcells_per_s": round(prob.updates / t / 1e9, 1)})
+        log(f"  paper {rows[-1]}")
+        plan.close()
+        del x, y
+        torch.cuda.empty_cache()
+    return {"workload": "the paper's benchmark stencils at its domain sizes (x fastest), FP64", "per_stencil": rows}
+
+
+def measured_clock_ghz(kernel_tag: str):
+    """Clock under the kernel from the committed SQ/GRBM summary, or None when
+    the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "tb2d_sq_counters_2d_suite_8192.md")
+    if not os.path.exists(path):
+        return None
+    src = None
+    for line in open(path).read().splitlines():
+        if line.startswith("kernel source hash:"):
+            src = line.split(":", 1)[1].strip()
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 3 and cells[0] == kernel_tag and src == kernel_source_hash():
+            try:
+                return float(cells[2])
+            except ValueError:
+                return None
+    return None
+
+
+def bench_model_calibration(np, stencil, breakdown, B_gbs):
+    """The attainable-performance model (paper Section 5) per suite stencil,
+    at spec parameters (8 TB/s, 78.6 TF) and calibrated ones (the copy
+    bandwidth measured in this run; the FP64 peak scaled by the clock measured
+    under that kernel), against the measured rate."""
+    rows = []
+    for row in breakdown:
+        d, r, k = row["depth"], row["radius"], row["points"]
+        V = 4
+        tile = (64.0 * V, row["seg_len"] + 2.0 * d * r)
+        tag = f"tb2d<double,{r},{row['pattern_code']},{d}>"
+        clock = measured_clock_ghz(tag)
+        out = {"stencil": row["stencil"], "measured": row["gcells_per_s"]}
+        for name, B, F in (("spec", 8.0e12, FP64_VALU_TFLOPS * 1e12),
+                           ("calibrated", B_gbs * 1e9, FP64_VALU_TFLOPS * 1e12 * (clock or 2.4) / 2.4)):
+            m = stencil.stencil_model_eval(B_gm=B, thr_cmp=F, cell_bytes=8.0, a_gm=2.0, a_cmp=2.0 * k,
+                                           D_gm=1.0, D_cmp=1.0, D_all=1.0, t=float(d),
+                                           tiling=stencil.MODEL_SM_TILING, tiled_dims=2,
+                                           tile=tile, rad=float(r))
+            out[f"model_{name}"] = round(m["PP"] / 1e9, 1)
+            out[f"measured_over_{name}"] = round(row["gcells_per_s"] / (m["PP"] / 1e9), 3)
+        out["clock_ghz"] = clock
+        rows.append(out)
+    return {"note": "PP = P x V with SM-tiling valid fraction; calibrated: B = copy bandwidth of this run, "
+                    "F = 78.6 TF x clock / 2.4 GHz", "per_stencil": rows}
+
+
 def bench_batch(torch, np, stencil, workloads):
     """128 heterogeneous grids, one batched submission per dtype."""
     probs = workloads.batch_problems()
@@ -399,8 +475,8 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--T", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -563,6 +639,10 @@ def main():
     del xs, ys
     torch.cuda.empty_cache()
     if not args.no_extras:
+        log("model calibration ...")
+        result["model_calibration"] = bench_model_calibration(np, stencil, breakdown, B)
+        log("paper benchmarks ...")
+        result["paper_benchmarks"] = bench_paper_benchmarks(torch, np, stencil, workloads)
         log("small Jacobi ...")
         result["small_jacobi"] = bench_small_jacobi(torch, np, stencil, workloads)
         log("3D suite ...")

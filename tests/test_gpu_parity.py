@@ -200,3 +200,13 @@ def test_3d_general_pattern():
     u0 = wl.make_field((12, 70, 70), 1, 88)
     info = _check(w, 1, u0, 3)
     assert info["pattern_name"] == "general"
+
+
+@pytest.mark.parametrize("kind", ["p17", "p19"])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_parity_paper_3d_point_sets(kind, dtype):
+    """The paper's 17- and 19-point 3D benchmark stencils (general pattern path)."""
+    w = wl.poisson_like_coeffs(3, kind, 1, 91)
+    u0 = wl.make_field((37, 70, 90), 1, 91, dtype)
+    info = _check(w, 1, u0, 5)
+    assert info["scheme_name"] == "blocked_3d" and info["pattern_name"] == "general", info
