@@ -6,9 +6,12 @@
 namespace stencil_impl {
 
 hipError_t batch_launch_f64(const void* params, int grid, size_t lds, hipStream_t s);
+hipError_t batch_launch_f64_aux(const void* params, int grid, size_t lds, hipStream_t s);
 hipError_t batch_launch_f32(const void* params, int grid, size_t lds, hipStream_t s);
 
-hipError_t batch_launch(int dtype, const void* params, int grid, size_t lds_bytes, hipStream_t stream) {
+hipError_t batch_launch(int dtype, const void* params, int grid, size_t lds_bytes, hipStream_t stream,
+                        bool aux) {
+  if (aux) return dtype == kF64 ? batch_launch_f64_aux(params, grid, lds_bytes, stream) : hipErrorInvalidValue;
   if (dtype == kF64) return batch_launch_f64(params, grid, lds_bytes, stream);
   if (dtype == kF32) return batch_launch_f32(params, grid, lds_bytes, stream);
   return hipErrorInvalidValue;
@@ -19,6 +22,11 @@ int batch_max_depth(int dtype, int ndim, int r, int shape) {
   if (ndim == 3 && r > 2) return 0;
   if (ndim != 2 && ndim != 3) return 0;
   return batch::batch_depth_c(dtype, ndim, r, shape);
+}
+
+int batch_aux_depth(int dtype, int ndim, int r, int shape) {
+  if (r < 1 || r > kMaxR || shape < kStar || shape > kGeneral) return 0;
+  return batch::aux_depth_c(dtype, ndim, r, shape);
 }
 
 namespace {

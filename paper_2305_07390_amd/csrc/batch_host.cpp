@@ -121,8 +121,10 @@ PinnedWord* pinned_word() {
 
 struct Group {
   int dtype;
+  bool aux = false;       // runs on the auxiliary batch kernel
   std::vector<int> jobs;  // indices into the batch
 };
+constexpr int kAuxGroup = 2;  // groups: kF32, kF64, then the FP64 auxiliary group
 
 // Work-list items of one pass: a 3D tile, or up to four 2D wave tiles.
 int64_t items_per_pass(const stencil_plan_s* p) {
@@ -201,10 +203,13 @@ namespace stencil_impl {
 stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::vector<const void*>& ins,
                          const std::vector<void*>& outs, const std::vector<void*>& wsg, hipStream_t s) {
   const int n = (int)plans.size();
-  // groups of blocked jobs by dtype; everything else runs alone
-  Group groups[2];
+  // groups of blocked jobs by dtype (the fused kernel), FP64 jobs of the
+  // auxiliary kernel's variants; everything else runs alone
+  Group groups[3];
   groups[kF32].dtype = kF32;
   groups[kF64].dtype = kF64;
+  groups[kAuxGroup].dtype = kF64;
+  groups[kAuxGroup].aux = true;
   std::vector<int> alone;
   for (int i = 0; i < n; ++i) {
     stencil_plan_s* p = plans[i];
@@ -213,6 +218,8 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     const bool blocked = p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D;
     if (blocked && p->depth <= batch_max_depth(dt, p->ndim, p->r, p->pattern))
       groups[dt].jobs.push_back(i);
+    else if (blocked && dt == kF64 && p->depth <= batch_aux_depth(dt, p->ndim, p->r, p->pattern))
+      groups[kAuxGroup].jobs.push_back(i);
     else
       alone.push_back(i);
   }
@@ -237,11 +244,12 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     int64_t hq_stride = 0;  // LDS halo elements per wave (2D jobs)
     size_t lds = 0;
   };
-  GroupMem gmem[2];
-  for (int d = 0; d < 2; ++d) {
-    Group& g = groups[d];
+  GroupMem gmem[3];
+  for (int gi = 0; gi < 3; ++gi) {
+    Group& g = groups[gi];
     if (g.jobs.empty()) continue;
-    GroupMem& m = gmem[d];
+    const int d = g.dtype;
+    GroupMem& m = gmem[gi];
     build_worklist(plans, g.jobs, m.cj, m.cp, m.cf);
     const size_t job_sz = d == kF64 ? sizeof(BatchJob<double>) : sizeof(BatchJob<float>);
     const size_t elem = d == kF64 ? 8 : 4;
@@ -265,8 +273,9 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     m.lds = std::max(m.lds, (size_t)(4 * m.hq_stride) * elem);
   }
   std::vector<FrameCopyJob> frames[2];  // per dtype
-  for (int d = 0; d < 2; ++d)
-    for (int i : groups[d].jobs) {
+  for (int gi = 0; gi < 3; ++gi)
+    for (int i : groups[gi].jobs) {
+      const int d = groups[gi].dtype;
       const stencil_plan_s* p = plans[i];
       FrameCopyJob f;
       std::memset(&f, 0, sizeof(f));
@@ -287,9 +296,9 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     frames_off[d] = total;
     total = align256(total + sizeof(FrameCopyJob) * frames[d].size());
   }
-  for (int d = 0; d < 2; ++d)
-    if (gmem[d].lds > (size_t)160 * 1024) {
-      return fail(STENCIL_ERR_UNSUPPORTED, "batch needs %zu bytes of LDS per workgroup", gmem[d].lds);
+  for (int gi = 0; gi < 3; ++gi)
+    if (gmem[gi].lds > (size_t)160 * 1024) {
+      return fail(STENCIL_ERR_UNSUPPORTED, "batch needs %zu bytes of LDS per workgroup", gmem[gi].lds);
     }
 
   if (total) {
@@ -308,17 +317,17 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
   // host image of the control region (everything after the workspaces is
   // small); counters start at zero
   size_t ctl_lo = total;
-  for (int d = 0; d < 2; ++d) {
-    if (!groups[d].jobs.empty()) ctl_lo = std::min(ctl_lo, gmem[d].jobs_off);
-    ctl_lo = std::min(ctl_lo, frames_off[d]);
-  }
+  for (int gi = 0; gi < 3; ++gi)
+    if (!groups[gi].jobs.empty()) ctl_lo = std::min(ctl_lo, gmem[gi].jobs_off);
+  for (int d = 0; d < 2; ++d) ctl_lo = std::min(ctl_lo, frames_off[d]);
   std::vector<char> img(total - ctl_lo, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(img.data() + (off - ctl_lo), src, bytes);
   };
-  for (int d = 0; d < 2; ++d) {
-    Group& g = groups[d];
-    GroupMem& m = gmem[d];
+  for (int gi = 0; gi < 3; ++gi) {
+    Group& g = groups[gi];
+    GroupMem& m = gmem[gi];
+    const int d = g.dtype;
     for (size_t local = 0; local < g.jobs.size(); ++local) {
       const int i = g.jobs[local];
       const stencil_plan_s* p = plans[i];
@@ -336,14 +345,18 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     put(m.cp_off, m.cp.data(), 4 * m.cp.size());
     put(m.cf_off, m.cf.data(), 8 * m.cf.size());
   }
-  for (int d = 0; d < 2; ++d) {
-    // second entry of a pair targets the job's workspace
-    size_t k = 0;
-    for (int i : groups[d].jobs) {
-      ++k;  // the `out` entry
-      if (plans[i]->workspace) frames[d][k++].dst = ws_of(i);
+  {
+    // second entry of a pair targets the job's workspace (same order as above)
+    size_t k[2] = {0, 0};
+    for (int gi = 0; gi < 3; ++gi) {
+      const int d = groups[gi].dtype;
+      for (int i : groups[gi].jobs) {
+        ++k[d];  // the `out` entry
+        if (plans[i]->workspace) frames[d][k[d]++].dst = ws_of(i);
+      }
     }
-    put(frames_off[d], frames[d].data(), sizeof(FrameCopyJob) * frames[d].size());
+    for (int d = 0; d < 2; ++d)
+      put(frames_off[d], frames[d].data(), sizeof(FrameCopyJob) * frames[d].size());
   }
   hipError_t e = hipSuccess;
   if (!img.empty()) e = upload_control(dev + ctl_lo, img.data(), img.size(), s);
@@ -356,10 +369,11 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     e = frame_copy_batch_launch(d, (const FrameCopyJob*)(dev + frames_off[d]), (int)frames[d].size(), s);
     if (e != hipSuccess) st = hip_fail(e, "batch halo copy");
   }
-  for (int d = 0; d < 2 && st == STENCIL_OK; ++d) {
-    Group& g = groups[d];
+  for (int gi = 0; gi < 3 && st == STENCIL_OK; ++gi) {
+    Group& g = groups[gi];
     if (g.jobs.empty()) continue;
-    GroupMem& m = gmem[d];
+    GroupMem& m = gmem[gi];
+    const int d = g.dtype;
     BatchQueue q;
     q.chunk_job = (const int32_t*)(dev + m.cj_off);
     q.chunk_pass = (const int32_t*)(dev + m.cp_off);
@@ -374,7 +388,7 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, q.nitems));
     if (d == kF64) {
       BatchParams<double> prm{(const BatchJob<double>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
-      e = batch_launch(d, &prm, grid, m.lds, s);
+      e = batch_launch(d, &prm, grid, m.lds, s, g.aux);
     } else {
       BatchParams<float> prm{(const BatchJob<float>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
       e = batch_launch(d, &prm, grid, m.lds, s);
@@ -430,8 +444,9 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     if (status[i] == STENCIL_OK &&
         (pl->scheme == STENCIL_SCHEME_BLOCKED_2D || pl->scheme == STENCIL_SCHEME_BLOCKED_3D)) {
       // the fused batch kernel's own depth limit for this variant
-      const int cap = batch_max_depth(pl->dtype == STENCIL_F64 ? kF64 : kF32, pl->ndim, pl->r,
-                                      pl->pattern);
+      const int dt = pl->dtype == STENCIL_F64 ? kF64 : kF32;
+      int cap = batch_max_depth(dt, pl->ndim, pl->r, pl->pattern);
+      if (cap == 0) cap = batch_aux_depth(dt, pl->ndim, pl->r, pl->pattern);
       if (cap >= 1 && pl->depth > cap) {
         stencil_plan_destroy(pl);
         pl = nullptr;

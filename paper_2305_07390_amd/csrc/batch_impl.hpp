@@ -127,9 +127,9 @@ __device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int ti
 }
 
 // One workgroup tile of a 3D job (the tb3d xy-tile/z-segment decomposition).
-template <typename Real, int R, int SHAPE>
+template <typename Real, int R, int SHAPE,
+          int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 3, R, SHAPE)>
 __device__ __forceinline__ void run_3d(const BatchJob<Real>& J, int pass, int tile, char* lds) {
-  constexpr int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 3, R, SHAPE);
   if constexpr (DEPTH > 0) {
     using namespace tb3d;
     constexpr int BY = cells_y(sizeof(Real) == 8, R, SHAPE);
@@ -161,14 +161,22 @@ __device__ __forceinline__ void run_3d(const BatchJob<Real>& J, int pass, int ti
   }
 }
 
+// Variants of the auxiliary batch kernel (SET 1): FP64 3D radius-2 stars,
+// which the fused kernel leaves out (4 x 2 cells per lane at depth 2 spill in
+// its shared register allocation). Alone in a kernel they fit, so their jobs
+// are still fused among themselves instead of running one after another.
+constexpr int aux_depth_c(int dtype, int ndim, int r, int shape) {
+  return (dtype == kF64 && ndim == 3 && r == 2 && shape == kStar) ? tb3d::max_depth_c(kF64, 2, kStar) : 0;
+}
+
 // The persistent batch kernel of one dtype: every compiled 2D and 3D variant
-// behind one work list. A workgroup claims an item (a 3D tile, or up to four
+// behind one work list (SET 0), or the auxiliary variants (SET 1). A workgroup claims an item (a 3D tile, or up to four
 // 2D tiles of one pass, one per wave), waits for the job's previous pass, runs
 // it and publishes the tiles done. Loop control is workgroup-uniform: wave 0
 // claims and waits, the result travels through LDS behind a barrier, and no
 // lane-dependent branch sits in the loop (the optimizer may thread a loop edge
 // on such a predicate and skip the claim).
-template <typename Real>
+template <typename Real, int SET>
 __global__ __launch_bounds__(256) void batch_kernel(const BatchParams<Real> p) {
   extern __shared__ char lds_raw[];
   __shared__ long long s_item;
@@ -199,7 +207,11 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchParams<Real> p) {
     const bool ok = __builtin_amdgcn_readfirstlane(s_ok) != 0;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave sees the previous pass
     unsigned ndone = 1;
-    if (variant < kBatch3DBase) {
+    if constexpr (SET == 1) {
+      if (ok && variant == batch_variant(3, 2, kStar))
+        run_3d<Real, 2, kStar, aux_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 3, 2, kStar)>(J, pass, sub,
+                                                                                           lds_raw);
+    } else if (variant < kBatch3DBase) {
       const int first = 4 * sub;
       ndone = (unsigned)((tiles - first) < 4 ? (tiles - first) : 4);
       const int t = first + wid;
@@ -243,9 +255,9 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchParams<Real> p) {
 namespace stencil_impl {
 namespace batch {
 
-template <typename Real>
+template <typename Real, int SET>
 hipError_t launch(const BatchParams<Real>* p, int grid, size_t lds, hipStream_t s) {
-  const void* fn = (const void*)&batch_kernel<Real>;
+  const void* fn = (const void*)&batch_kernel<Real, SET>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   void* args[] = {(void*)p};

@@ -110,10 +110,15 @@ struct FrameCopyJob {
 };
 
 // The fused persistent batch kernel of a dtype (grid workgroups of 256).
-hipError_t batch_launch(int dtype, const void* params, int grid, size_t lds_bytes, hipStream_t stream);
+// aux: the auxiliary kernel (batch_aux_depth) instead of the fused one
+hipError_t batch_launch(int dtype, const void* params, int grid, size_t lds_bytes, hipStream_t stream,
+                        bool aux = false);
 // Deepest compiled depth of a batched variant (0: none), and the LDS bytes a
 // 3D variant needs.
 int batch_max_depth(int dtype, int ndim, int r, int shape);
+// Deepest variant of the auxiliary batch kernel (0: none), for variants the
+// fused kernel leaves out.
+int batch_aux_depth(int dtype, int ndim, int r, int shape);
 size_t batch_lds_3d(int dtype, int r, int shape);
 // Device-wide barrier probe (one workgroup per CU), see stencil_probe_grid_sync.
 hipError_t grid_sync_probe_launch(unsigned int* ctr, unsigned int* err, int rounds, int grid,

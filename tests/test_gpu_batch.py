@@ -79,3 +79,24 @@ def test_batch_reports_invalid_jobs():
     for k in (0, 2):
         ref = oracle.sweep(probs[k].coeffs, probs[k].spec.r, probs[k].field(), probs[k].T)
         assert np.array_equal(ys[k].cpu().numpy(), ref)
+
+
+def test_batch_fp64_3d_radius2_jobs_fused_apart():
+    """FP64 3D radius-2 stars take the auxiliary batch kernel (several jobs of
+    different shapes and T next to a 2D job); each equals the oracle."""
+    import torch
+    spec = wl.StencilSpec("3d_star_r2", 3, "star", 2)
+    shapes = [((20, 64, 70), 4), ((33, 70, 96), 6), ((12, 80, 64), 3), ((40, 64, 130), 5)]
+    probs = [wl.Problem(spec, wl.coeffs_for(spec, 300 + g), shp, T, field_seed=310 + g, tag=g)
+             for g, (shp, T) in enumerate(shapes)]
+    s2 = wl.StencilSpec("2d_star_r1", 2, "star", 1)
+    probs.append(wl.Problem(s2, wl.coeffs_for(s2, 320), (300, 600), 13, field_seed=321, tag=9))
+    fields = [p.field(np.float64) for p in probs]
+    xs = [torch.from_numpy(f).cuda() for f in fields]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    status = st.run_batch(probs, xs, ys)
+    assert all(s == st.STENCIL_OK for s in status), status
+    st.stencil_sync(torch.cuda.current_stream().cuda_stream)
+    for p, f, y in zip(probs, fields, ys):
+        ref = oracle.sweep(p.coeffs, p.spec.r, f, p.T)
+        assert np.array_equal(y.cpu().numpy(), ref), (p.spec.name, p.interior, p.T)
