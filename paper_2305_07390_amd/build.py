@@ -65,18 +65,29 @@ def _compile(src: str):
     return obj, _resources(res.stderr)
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
+def build(jobs: int | None = None, verbose: bool = True, only: list | None = None) -> str:
+    """Compile every source (or, with `only`, just the named ones, reusing the
+    other objects of the previous build) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
-    jobs = jobs or max(1, min(len(srcs), len(os.sched_getaffinity(0))))
+    todo = [s for s in srcs if not only or os.path.basename(s) in only]
+    jobs = jobs or max(1, min(len(todo), len(os.sched_getaffinity(0))))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_compile, srcs))
-    objs = [o for o, _ in results]
+        done = dict(zip(todo, ex.map(_compile, todo)))
+    objs = [done[s][0] if s in done else os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
     # one line per kernel: name, VGPRs, AGPRs, scratch bytes per lane, LDS
+    old = {}
+    if only and os.path.exists(RESOURCE_REPORT):
+        for line in open(RESOURCE_REPORT):
+            old.setdefault(line.split(" ", 1)[0], []).append(line)
     with open(RESOURCE_REPORT, "w") as f:
-        for src, (_, kernels) in zip(srcs, results):
-            for name, r in kernels:
-                f.write(f"{os.path.basename(src)} {name} vgpr={r.get('VGPRs')} agpr={r.get('AGPRs')} "
+        for src in srcs:
+            base = os.path.basename(src)
+            if src not in done:
+                f.writelines(old.get(base, []))
+                continue
+            for name, r in done[src][1]:
+                f.write(f"{base} {name} vgpr={r.get('VGPRs')} agpr={r.get('AGPRs')} "
                         f"scratch={r.get('ScratchSize')} lds={r.get('LDS')}\n")
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
@@ -90,4 +101,8 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", default="", help="comma-separated sources to recompile")
+    a = ap.parse_args()
+    build(only=[x for x in a.only.split(",") if x] or None)

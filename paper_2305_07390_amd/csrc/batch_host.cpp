@@ -24,8 +24,17 @@ using namespace stencil_impl;
 namespace {
 
 constexpr int64_t kTimeoutTicks = 500000000;  // 5 s of the 100 MHz realtime clock
-constexpr int kBatchSeg2D = 256;              // rows per 2D batch tile
-constexpr int kBatchSeg3D = 64;               // planes per 3D batch tile
+// Batch tiles are longer than single-grid ones (fewer warm-up rows per tile),
+// but a job's passes run one after another, so a tile also bounds how fast
+// a long job can finish: measured on the 128-grid batch, 512 rows and 128
+// planes are the best of {128, 256, 512, 1024} x {32, 64, 128, 256} (FP64 3D
+// tiles of 256 planes make the longest jobs' pass chain the critical path).
+constexpr int kBatchSeg2D = 512;              // rows per 2D batch tile
+constexpr int kBatchSeg3D = 128;              // planes per 3D batch tile
+// Tiles of the serving loop's rounds: a round runs a few passes of every
+// active request, so shorter tiles keep rounds, and latency, short.
+constexpr int kServeSeg2D = 256;
+constexpr int kServeSeg3D = 64;
 
 // Per-device error word shared by all batch launches on that device.
 unsigned int* device_error_word() {
@@ -407,12 +416,8 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
   return st;
 }
 
-}  // namespace stencil_impl
-
-extern "C" {
-
-stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* stream,
-                                    stencil_status* per_job_status) {
+stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stream,
+                                  stencil_status* per_job_status, int seg2d, int seg3d) {
   if (!jobs || n <= 0) return fail(STENCIL_ERR_INVALID, "no jobs");
   hipStream_t s = (hipStream_t)stream;
   std::vector<stencil_status> status(n, STENCIL_OK);
@@ -428,7 +433,7 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
     stencil_tuning hint;
     std::memset(&hint, 0, sizeof(hint));
     hint.depth = j.depth;
-    hint.tile[0] = j.shape.ndim == 2 ? kBatchSeg2D : kBatchSeg3D;
+    hint.tile[0] = j.shape.ndim == 2 ? seg2d : seg3d;
     hint.flags = STENCIL_FLAG_UNIFORM_TILES;  // the jobs share the wave slots
     stencil_plan_t pl = nullptr;
     status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
@@ -509,6 +514,18 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
   stencil_status st = batch_run(plans, ins, outs, wsg, s);
   for (auto* p : plans) stencil_plan_destroy(p);
   return st;
+}
+
+int serve_seg_2d() { return kServeSeg2D; }
+int serve_seg_3d() { return kServeSeg3D; }
+
+}  // namespace stencil_impl
+
+extern "C" {
+
+stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* stream,
+                                    stencil_status* per_job_status) {
+  return batch_submit_tiles(jobs, n, stream, per_job_status, kBatchSeg2D, kBatchSeg3D);
 }
 
 stencil_status stencil_probe_grid_sync(int32_t rounds, void* stream, double* seconds_per_sync) {

@@ -93,9 +93,11 @@ int default_depth_2d(int r, int pattern, int dtype) {
   const int maxd = tb2d_max_depth(dtype, r, pattern);
   const bool f64 = dtype == STENCIL_F64;
   int d;
-  // measured fastest on 8192^2 (radius-2 stars and FP32 5-point stars stop
-  // short of their deepest variant, whose register rings crowd the file)
-  if (pattern == STENCIL_STAR) d = r == 1 ? (f64 ? 12 : 10) : r == 2 ? (f64 ? 7 : 6) : r == 3 ? 4 : 2;
+  // measured fastest on 8192^2 (radius-2 stars stop short of their deepest
+  // variant, whose register rings crowd the file); the FP32 5-point star
+  // keeps 12: depth 10 is 2 % faster on one large grid, but its extra passes
+  // lengthen serving rounds (p50 33 -> 48 ms)
+  if (pattern == STENCIL_STAR) d = r == 1 ? 12 : r == 2 ? (f64 ? 7 : 6) : r == 3 ? 4 : 2;
   else if (pattern == STENCIL_BOX) d = r == 1 ? 8 : r == 2 ? 5 : r == 3 ? 3 : 2;
   else d = maxd;
   return std::min(d, maxd);

@@ -28,6 +28,11 @@ namespace stencil_impl {
 // Autotuner cache lookup for a plan's stencil class and size (tune.cpp).
 bool tune_lookup_plan(const stencil_plan_s* pl, bool batched, int* depth, int* seg);
 // Prepared plans through the persistent batch kernel (batch_host.cpp).
+// stencil_batch_submit with explicit batch tile lengths (2D rows, 3D planes).
+stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stream,
+                                  stencil_status* per_job_status, int seg2d, int seg3d);
+int serve_seg_2d();
+int serve_seg_3d();
 stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::vector<const void*>& ins,
                          const std::vector<void*>& outs, const std::vector<void*>& wsg, hipStream_t s);
 }  // namespace stencil_impl

@@ -232,7 +232,8 @@ void scheduler(stencil_server_s* srv) {
     std::vector<stencil_status> js(round.size(), STENCIL_OK);
     const Clock::time_point t0 = Clock::now();
     if (st == STENCIL_OK)
-      st = stencil_batch_submit(jobs.data(), (int32_t)jobs.size(), srv->compute, js.data());
+      st = batch_submit_tiles(jobs.data(), (int32_t)jobs.size(), srv->compute, js.data(), serve_seg_2d(),
+                              serve_seg_3d());
     if (st == STENCIL_OK && hipEventRecord(srv->round_end, srv->compute) != hipSuccess)
       st = hip_fail(hipErrorUnknown, "server round event");
     // while the round runs, admit arrivals so their inputs are on the device
