@@ -210,3 +210,14 @@ def test_parity_paper_3d_point_sets(kind, dtype):
     u0 = wl.make_field((37, 70, 90), 1, 91, dtype)
     info = _check(w, 1, u0, 5)
     assert info["scheme_name"] == "blocked_3d" and info["pattern_name"] == "general", info
+
+
+@pytest.mark.parametrize("kind,r", [("star", 1), ("box", 1), ("star", 2), ("p19", 1)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_parity_3d_interior_tiles(kind, r, dtype):
+    """Grids wide enough for tiles with redundant margins on all four sides,
+    whose face values come from neighbouring tiles' stale data."""
+    w = wl.poisson_like_coeffs(3, kind, r, 93)
+    u0 = wl.make_field((14, 200, 300), r, 93, dtype)
+    info = _check(w, r, u0, 9)
+    assert info["scheme_name"] == "blocked_3d" and info["strips"] >= 16, info
