@@ -137,6 +137,48 @@ def measured_traffic(kernel_tag: str):
     return None
 
 
+def probe3d():
+    """Short program for 3D counter passes: two passes of each 3D suite stencil
+    (512^3, FP64 and FP32) at its planned depth."""
+    import numpy as np
+    import torch
+
+    from paper_2305_07390_amd import stencil, workloads
+    torch.cuda.set_device(0)
+    for prob in workloads.suite_3d_problems(512, 200):
+        for dt in (np.float64, np.float32):
+            x = torch.from_numpy(prob.field(dt)).cuda()
+            y = torch.empty_like(x)
+            full = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, dt, prob.T)
+            d = full.info["depth"]
+            full.close()
+            plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, dt, 2 * d)
+            plan.execute(x, y)
+            torch.cuda.synchronize()
+            log(f"probe3d: {prob.spec.name} {np.dtype(dt).name} depth {d} passes {plan.info['passes']}")
+            plan.close()
+            del x, y
+            torch.cuda.empty_cache()
+
+
+def probe_batch():
+    """One run of the 128-grid batch per dtype (for kernel traces)."""
+    import numpy as np
+    import torch
+
+    from paper_2305_07390_amd import stencil, workloads
+    torch.cuda.set_device(0)
+    probs = workloads.batch_problems()
+    for dt in (np.float64, np.float32):
+        xs = [torch.from_numpy(p.field(np.float64).astype(dt)).cuda() for p in probs]
+        ys = [torch.empty_like(x) for x in xs]
+        stencil.run_batch(probs, xs, ys)
+        stencil.stencil_sync()
+        log(f"probe batch: {np.dtype(dt).name} {len(probs)} grids")
+        del xs, ys
+        torch.cuda.empty_cache()
+
+
 def probe():
     """Short program for PMC passes: a 512 MiB device copy (counter
     calibration) and two passes of each suite stencil at its planned depth."""
@@ -486,9 +528,19 @@ def main():
     ap.add_argument("--depth", type=int, default=0, help="force a temporal depth (0 = plan)")
     ap.add_argument("--probe", action="store_true",
                     help="run the short program used for PMC counter passes and exit")
+    ap.add_argument("--probe3d", action="store_true",
+                    help="run the short 3D program used for counter passes and exit")
+    ap.add_argument("--probe-batch", action="store_true",
+                    help="run the 128-grid batch once per dtype and exit")
     args = ap.parse_args()
     if args.probe:
         probe()
+        return
+    if args.probe3d:
+        probe3d()
+        return
+    if args.probe_batch:
+        probe_batch()
         return
 
     if args.gpus != 1:
