@@ -24,6 +24,25 @@ int batch_max_depth(int dtype, int ndim, int r, int shape) {
   return batch::batch_depth_c(dtype, ndim, r, shape);
 }
 
+hipError_t batch_launch_single_f64(int variant, const void* params, int grid, size_t lds, hipStream_t s);
+hipError_t batch_launch_single_f32(int variant, const void* params, int grid, size_t lds, hipStream_t s);
+
+hipError_t batch_launch_single(int dtype, int variant, const void* params, int grid, size_t lds_bytes,
+                               hipStream_t stream) {
+  if (dtype == kF64) return batch_launch_single_f64(variant, params, grid, lds_bytes, stream);
+  if (dtype == kF32) return batch_launch_single_f32(variant, params, grid, lds_bytes, stream);
+  return hipErrorInvalidValue;
+}
+
+bool batch_single_supported(int dtype, int ndim, int r, int shape) {
+  if (shape < kStar || shape > kGeneral || (ndim != 2 && ndim != 3)) return false;
+  return batch::single_supported(dtype, ndim, r, shape);
+}
+
+int batch_single_depth(int dtype, int ndim, int r, int shape) {
+  return batch_single_supported(dtype, ndim, r, shape) ? batch::single_depth_c(dtype, ndim, r, shape) : 0;
+}
+
 int batch_aux_depth(int dtype, int ndim, int r, int shape) {
   if (r < 1 || r > kMaxR || shape < kStar || shape > kGeneral) return 0;
   return batch::aux_depth_c(dtype, ndim, r, shape);

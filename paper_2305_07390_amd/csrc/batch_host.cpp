@@ -220,7 +220,15 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
   groups[kAuxGroup].dtype = kF64;
   groups[kAuxGroup].aux = true;
   std::vector<int> alone;
-  for (int i = 0; i < n; ++i) {
+  // a persistent single-grid plan runs on its variant's own persistent kernel
+  int single_variant = -1;
+  if (n == 1 && plans[0] && plans[0]->persistent) {
+    stencil_plan_s* p = plans[0];
+    const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
+    single_variant = batch_variant(p->ndim, p->r, p->pattern);
+    groups[dt].jobs.push_back(0);
+  }
+  for (int i = 0; i < n && single_variant < 0; ++i) {
     stencil_plan_s* p = plans[i];
     if (!p) continue;
     const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
@@ -397,10 +405,12 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, q.nitems));
     if (d == kF64) {
       BatchParams<double> prm{(const BatchJob<double>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
-      e = batch_launch(d, &prm, grid, m.lds, s, g.aux);
+      e = single_variant >= 0 ? batch_launch_single(d, single_variant, &prm, grid, m.lds, s)
+                              : batch_launch(d, &prm, grid, m.lds, s, g.aux);
     } else {
       BatchParams<float> prm{(const BatchJob<float>*)(dev + m.jobs_off), q, (int32_t)m.hq_stride};
-      e = batch_launch(d, &prm, grid, m.lds, s);
+      e = single_variant >= 0 ? batch_launch_single(d, single_variant, &prm, grid, m.lds, s)
+                              : batch_launch(d, &prm, grid, m.lds, s);
     }
     if (e != hipSuccess) st = hip_fail(e, "batch launch");
   }

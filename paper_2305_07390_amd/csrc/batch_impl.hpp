@@ -92,9 +92,9 @@ constexpr int batch_depth_c(int dtype, int ndim, int r, int shape) {
 }
 
 // One wave tile of a 2D job (the tb2d strip/segment decomposition).
-template <typename Real, int R, int SHAPE>
+template <typename Real, int R, int SHAPE,
+          int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 2, R, SHAPE)>
 __device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int tile, Real* hq, int lane) {
-  constexpr int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 2, R, SHAPE);
   if constexpr (DEPTH > 0) {
     constexpr int V = tb2d_cols(sizeof(Real) == 8, R, SHAPE);
     constexpr int KB = (2 * R + 1) * (2 * R + 1);
@@ -128,7 +128,7 @@ __device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int ti
 
 // One workgroup tile of a 3D job (the tb3d xy-tile/z-segment decomposition).
 template <typename Real, int R, int SHAPE,
-          int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 3, R, SHAPE)>
+          int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 3, R, SHAPE), int Z0 = 2>
 __device__ __forceinline__ void run_3d(const BatchJob<Real>& J, int pass, int tile, char* lds) {
   if constexpr (DEPTH > 0) {
     using namespace tb3d;
@@ -155,9 +155,9 @@ __device__ __forceinline__ void run_3d(const BatchJob<Real>& J, int pass, int ti
     const int Zs0 = seg * seg_len;
     const int Zs1 = (Zs0 + seg_len < Qz) ? Zs0 + seg_len : Qz;
     if (d == DEPTH)
-      tb3d_tile<Real, R, SHAPE, DEPTH, 2>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, DEPTH, faces, xchg);
+      tb3d_tile<Real, R, SHAPE, DEPTH, Z0>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, DEPTH, faces, xchg);
     else
-      tb3d_tile<Real, R, SHAPE, DEPTH, 2>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, d, faces, xchg);
+      tb3d_tile<Real, R, SHAPE, DEPTH, Z0>(wl, src, dst, P, Qy, Qz, g, Zs0, Zs1, d, faces, xchg);
   }
 }
 
@@ -169,8 +169,29 @@ constexpr int aux_depth_c(int dtype, int ndim, int r, int shape) {
   return (dtype == kF64 && ndim == 3 && r == 2 && shape == kStar) ? tb3d::max_depth_c(kF64, 2, kStar) : 0;
 }
 
+// Single-variant persistent kernels (SET = kSingleBase + variant id) run one
+// plan's passes in one launch (STENCIL_FLAG_PERSISTENT) with that variant's
+// own register allocation, at its single-grid depth and plane ring.
+constexpr int kSingleBase = 2;
+constexpr int set_ndim(int set) { return 2 + (set - kSingleBase) / kBatch3DBase; }
+constexpr int set_r(int set) { return ((set - kSingleBase) % kBatch3DBase) / 3 + 1; }
+constexpr int set_shape(int set) { return (set - kSingleBase) % 3; }
+// Depth and plane ring of a single-variant kernel: the single-grid ones,
+// except where the job descriptor's extra registers would spill (2D radius-2
+// stars stop at 7 / 6 as in the fused kernel; the FP64 3D 7-point star keeps
+// two planes in flight).
+constexpr int single_depth_c(int dtype, int ndim, int r, int shape) {
+  if (ndim == 2 && r == 2 && shape == kStar) return dtype == kF64 ? 7 : 6;
+  return ndim == 2 ? max_depth_c(r, shape) : tb3d::max_depth_c(dtype, r, shape);
+}
+constexpr int single_ring_c(int dtype, int r, int shape, int depth) {
+  return (dtype == kF64 && r == 1 && shape == kStar && depth == 4) ? 2
+                                                                   : tb3d::plane_ring(dtype == kF64, r, shape, depth);
+}
+
 // The persistent batch kernel of one dtype: every compiled 2D and 3D variant
-// behind one work list (SET 0), or the auxiliary variants (SET 1). A workgroup claims an item (a 3D tile, or up to four
+// behind one work list (SET 0), the auxiliary variants (SET 1), or one variant
+// (SET >= kSingleBase). A workgroup claims an item (a 3D tile, or up to four
 // 2D tiles of one pass, one per wave), waits for the job's previous pass, runs
 // it and publishes the tiles done. Loop control is workgroup-uniform: wave 0
 // claims and waits, the result travels through LDS behind a barrier, and no
@@ -207,10 +228,25 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchParams<Real> p) {
     const bool ok = __builtin_amdgcn_readfirstlane(s_ok) != 0;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave sees the previous pass
     unsigned ndone = 1;
-    if constexpr (SET == 1) {
+    constexpr int DT = sizeof(Real) == 8 ? kF64 : kF32;
+    if constexpr (SET >= kSingleBase) {
+      constexpr int ND = set_ndim(SET), RR = set_r(SET), SH = set_shape(SET);
+      constexpr int D = single_depth_c(DT, ND, RR, SH);
+      if constexpr (ND == 2) {
+        const int first = 4 * sub;
+        ndone = (unsigned)((tiles - first) < 4 ? (tiles - first) : 4);
+        const int t = first + wid;
+        if (ok && t < tiles) {
+          Real* hq = (Real*)lds_raw + (size_t)wid * p.hq_stride;
+          run_2d<Real, RR, SH, D>(J, pass, t, hq, lane);
+        }
+      } else if (ok) {
+        run_3d<Real, RR, SH, D, single_ring_c(DT, RR, SH, D)>(J, pass, sub, lds_raw);
+      }
+      (void)variant;
+    } else if constexpr (SET == 1) {
       if (ok && variant == batch_variant(3, 2, kStar))
-        run_3d<Real, 2, kStar, aux_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 3, 2, kStar)>(J, pass, sub,
-                                                                                           lds_raw);
+        run_3d<Real, 2, kStar, aux_depth_c(DT, 3, 2, kStar)>(J, pass, sub, lds_raw);
     } else if (variant < kBatch3DBase) {
       const int first = 4 * sub;
       ndone = (unsigned)((tiles - first) < 4 ? (tiles - first) : 4);
@@ -262,6 +298,29 @@ hipError_t launch(const BatchParams<Real>* p, int grid, size_t lds, hipStream_t 
   if (e != hipSuccess) return e;
   void* args[] = {(void*)p};
   return hipLaunchKernel(fn, dim3(grid), dim3(256), args, lds, s);
+}
+
+// Variants with a single-variant persistent kernel: every variant with a
+// blocked single-grid kernel.
+constexpr bool single_supported(int dtype, int ndim, int r, int shape) {
+  return r >= 1 && r <= (ndim == 2 ? kMaxR : 2) && single_depth_c(dtype, ndim, r, shape) > 0;
+}
+
+template <typename Real, int V>
+hipError_t launch_single_from(int variant, const BatchParams<Real>* p, int grid, size_t lds,
+                              hipStream_t s) {
+  if constexpr (V >= 2 * kBatch3DBase) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int SET = kSingleBase + V;
+    constexpr int DT = sizeof(Real) == 8 ? kF64 : kF32;
+    if (variant == V) {
+      if constexpr (single_supported(DT, set_ndim(SET), set_r(SET), set_shape(SET)))
+        return launch<Real, SET>(p, grid, lds, s);
+      return hipErrorInvalidValue;
+    }
+    return launch_single_from<Real, V + 1>(variant, p, grid, lds, s);
+  }
 }
 
 }  // namespace batch

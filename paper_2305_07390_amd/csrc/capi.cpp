@@ -481,8 +481,9 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
     const bool want_persistent = hint && (hint->flags & STENCIL_FLAG_PERSISTENT);
     if (want_persistent &&
         (p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D)) {
-      // the persistent kernel holds its own (possibly shallower) variants
-      const int cap = batch_max_depth(dtype == STENCIL_F64 ? kF64 : kF32, p->ndim, radius, p->pattern);
+      // one persistent kernel per variant, at the launches' depths where its
+      // registers allow
+      const int cap = batch_single_depth(dtype == STENCIL_F64 ? kF64 : kF32, p->ndim, radius, p->pattern);
       if (cap >= 1) {
         p->persistent = true;
         if (p->depth > cap) {

@@ -116,6 +116,12 @@ hipError_t batch_launch(int dtype, const void* params, int grid, size_t lds_byte
 // Deepest compiled depth of a batched variant (0: none), and the LDS bytes a
 // 3D variant needs.
 int batch_max_depth(int dtype, int ndim, int r, int shape);
+// Single-variant persistent kernel of `variant` (batch_variant id): one plan's
+// passes in one launch at the variant's single-grid depth.
+hipError_t batch_launch_single(int dtype, int variant, const void* params, int grid, size_t lds_bytes,
+                               hipStream_t stream);
+bool batch_single_supported(int dtype, int ndim, int r, int shape);
+int batch_single_depth(int dtype, int ndim, int r, int shape);
 // Deepest variant of the auxiliary batch kernel (0: none), for variants the
 // fused kernel leaves out.
 int batch_aux_depth(int dtype, int ndim, int r, int shape);

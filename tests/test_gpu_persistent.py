@@ -17,6 +17,9 @@ CASES = [
     ("2d13pt_star_r3", (512, 512), 17, np.float64),
     ("3d7pt_star_r1", (40, 70, 130), 9, np.float64),
     ("3d13pt_star_r2", (33, 64, 100), 7, np.float32),
+    ("3d13pt_star_r2", (30, 70, 96), 5, np.float64),
+    ("3d27pt_box_r1", (26, 70, 90), 5, np.float64),
+    ("2d9pt_box_r1", (300, 1100), 19, np.float32),
 ]
 
 
