@@ -92,8 +92,10 @@ constexpr int batch_depth_c(int dtype, int ndim, int r, int shape) {
 }
 
 // One wave tile of a 2D job (the tb2d strip/segment decomposition).
+// SPLIT: interior strips take the tile body without halo reads (as in the
+// single-grid kernel); the fused kernel keeps one body for all strips.
 template <typename Real, int R, int SHAPE,
-          int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 2, R, SHAPE)>
+          int DEPTH = batch_depth_c(sizeof(Real) == 8 ? kF64 : kF32, 2, R, SHAPE), bool SPLIT = false>
 __device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int tile, Real* hq, int lane) {
   if constexpr (DEPTH > 0) {
     constexpr int V = tb2d_cols(sizeof(Real) == 8, R, SHAPE);
@@ -117,7 +119,9 @@ __device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int ti
     // single-grid kernel; the remainder pass takes it at run time. One tile
     // body serves interior and edge strips here (the fused kernel's register
     // budget has no room for a second copy).
-    if (d == DEPTH)
+    if (SPLIT && d == DEPTH)
+      tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0, Y1, DEPTH);
+    else if (d == DEPTH)
       tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb,
                                                      Y0, Y1, DEPTH);
     else
@@ -238,7 +242,8 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchParams<Real> p) {
         const int t = first + wid;
         if (ok && t < tiles) {
           Real* hq = (Real*)lds_raw + (size_t)wid * p.hq_stride;
-          run_2d<Real, RR, SH, D>(J, pass, t, hq, lane);
+          // (one body for the FP32 radius-3 star, whose registers overflow with two)
+          run_2d<Real, RR, SH, D, !(DT == kF32 && RR == 3 && SH == kStar)>(J, pass, t, hq, lane);
         }
       } else if (ok) {
         run_3d<Real, RR, SH, D, single_ring_c(DT, RR, SH, D)>(J, pass, sub, lds_raw);
