@@ -281,12 +281,17 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchParams<Real> p) {
         default: break;
       }
     }
-    // every wave's stores are released before the count is published
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Publish the tiles: every wave's stores reach this XCD's L2 (workgroup
+    // release, ordered by the barrier), then wave 0 alone releases at agent
+    // scope, which writes back the whole L2 once for the workgroup, and adds
+    // the count.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
-    if (wave0)
-      __hip_atomic_fetch_add(q.done + job, lane == 0 ? ndone : 0u, __ATOMIC_RELEASE,
+    if (wave0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(q.done + job, lane == 0 ? ndone : 0u, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
