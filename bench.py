@@ -11,13 +11,21 @@ the roofline record of the dominant kernel (HBM or VALU, whichever bounds it),
 the per-stencil breakdown with the fraction of the temporally blocked roofline
 min(t_eff * B / 2S, F / 2k), and the CPU oracle timed on a bounded sample of
 the same workload. Unless --no-extras is given, the same line also reports the
-other workloads once each: the 3D single-grid suite (512^3, T=200, FP64), the
-heterogeneous batch of 128 grids in one persistent launch per dtype (FP64 and
-FP32, with the FP32 error against the FP64 result) and a short run of the
-serving loop under Poisson arrivals (FP32, p50/p99 latency).
+other workloads once each: the plain one-step kernel's rate, one grid-wide
+barrier's cost, the suite in persistent launches and with autotuned plans,
+the attainable-performance model next to each measured rate, the paper's
+benchmark stencils at its domain sizes, the small Jacobi latency, the 3D
+single-grid suite (512^3, T=200, FP64), the heterogeneous batch of 128 grids
+in one persistent launch per dtype (FP64 and FP32, with the FP32 error against
+the FP64 result and the fraction of its bytes/flops bound) and the serving
+loop under Poisson arrivals (FP32, 200 warm-up + measured requests, p50/p99
+latency, an FP32 error sample, FP64 plain throughput and a small-budget
+stress run).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--T 1000]
                        [--no-cpu] [--no-extras] [--serve-seconds S]
+       python bench.py --probe | --probe3d | --probe-batch   (short programs for
+                       rocprofv3 counter and trace passes)
 """
 from __future__ import annotations
 
