@@ -100,3 +100,29 @@ def test_batch_fp64_3d_radius2_jobs_fused_apart():
     for p, f, y in zip(probs, fields, ys):
         ref = oracle.sweep(p.coeffs, p.spec.r, f, p.T)
         assert np.array_equal(y.cpu().numpy(), ref), (p.spec.name, p.interior, p.T)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_batch_mixes_alone_jobs(dtype):
+    """Jobs without a batched variant (T = 0 copy, a grid narrower than one wave
+    tile, a 3D radius-2 box) run after the persistent launches, next to fused
+    jobs; each equals the oracle."""
+    import torch
+    specs = [
+        (wl.StencilSpec("2d_star_r1", 2, "star", 1), (40, 300), 0),      # copy
+        (wl.StencilSpec("2d_star_r1", 2, "star", 1), (50, 60), 7),       # plain kernel
+        (wl.StencilSpec("3d_box_r2", 3, "box", 2), (10, 20, 24), 3),     # no blocked 3D variant
+        (wl.StencilSpec("2d_box_r1", 2, "box", 1), (260, 700), 11),      # fused
+        (wl.StencilSpec("3d_star_r1", 3, "star", 1), (18, 70, 80), 6),   # fused
+    ]
+    probs = [wl.Problem(s, wl.coeffs_for(s, 400 + g), shp, T, field_seed=410 + g, tag=g)
+             for g, (s, shp, T) in enumerate(specs)]
+    fields = [p.field(dtype) for p in probs]
+    xs = [torch.from_numpy(f).cuda() for f in fields]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    status = st.run_batch(probs, xs, ys)
+    assert all(s == st.STENCIL_OK for s in status), status
+    st.stencil_sync(torch.cuda.current_stream().cuda_stream)
+    for p, f, y in zip(probs, fields, ys):
+        ref = oracle.sweep(p.coeffs, p.spec.r, f, p.T)
+        assert np.array_equal(y.cpu().numpy(), ref), (p.spec.name, p.interior, p.T)

@@ -56,3 +56,15 @@ def test_grid_sync_probe():
     st.stencil_sync()
     with pytest.raises(st.StencilError):
         st.stencil_probe_grid_sync(0)
+
+
+@pytest.mark.parametrize("T", [1, 3, 12])
+def test_persistent_single_pass_and_remainder(T):
+    """A persistent plan whose passes are one short pass, or one full pass."""
+    spec = {s.name: s for s in wl.ALL_STENCILS}["2d5pt_star_r1"]
+    coeffs = wl.coeffs_for(spec, 65)
+    u0 = wl.make_field((260, 900), 1, seed=66)
+    ref = oracle.sweep(coeffs, 1, u0, T)
+    got, info = gpu_sweep(coeffs, 1, u0, T, flags=st.STENCIL_FLAG_PERSISTENT, repeats=2, return_info=True)
+    assert info["passes"] == 1, info
+    np.testing.assert_array_equal(got, ref)
