@@ -434,7 +434,13 @@ __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
   const int Q = (int)a.Q;
   // strip layout shared by every pass of the plan: hl * V >= DEPTH * r
   const int HL = a.hl;
-  for (int tile = blockIdx.x * waves + wid; tile < a.ntiles; tile += stride) {
+  // Workgroups are dispatched round-robin over the 8 XCDs. Give each XCD a
+  // run of consecutive tile groups, so that adjacent strips, which re-read each
+  // other's margin columns, share an L2 (a bijection for any grid size).
+  const int g = (int)gridDim.x, xcd = (int)blockIdx.x % 8, slot = (int)blockIdx.x / 8;
+  const int per = g / 8, extra = g % 8;
+  const int swz = xcd * per + (xcd < extra ? xcd : extra) + slot;
+  for (int tile = swz * waves + wid; tile < a.ntiles; tile += stride) {
     const Tile2D g = locate_2d(tile, ns, a.seg_len, a.seg_len_e, a.edge_tiles, P, Q, R, V, HL);
     tb2d_tile<Real, R, SHAPE, DEPTH, V>(a.w, a.src, a.dst, a.orig, P, Q, hq, lane, g.edge, g.X0,
                                         g.la, g.lb, g.Y0, g.Y1, DEPTH);
