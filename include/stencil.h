@@ -183,9 +183,14 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
                                     stencil_status* per_job_status);
 
 /* Wait for `stream` and report device-side failures of the library's kernels
- * since the last call: STENCIL_ERR_TIMEOUT if a bounded wait expired (the
- * affected results are undefined), STENCIL_ERR_DEVICE if the stream reports an
- * error, else STENCIL_OK. */
+ * enqueued on that stream since the last call on it: STENCIL_ERR_TIMEOUT if a
+ * bounded wait expired (the affected results are undefined), STENCIL_ERR_DEVICE
+ * if the stream reports an error, else STENCIL_OK. Each launch has its own
+ * error word, so an expiry never affects the waits of other launches; a small
+ * kernel after each launch folds it into a report word of the stream, which
+ * this call reads and clears. The watchdog limit is 5 s per wait, or
+ * STENCIL_WATCHDOG_US microseconds when that environment variable is set
+ * (read at each launch). */
 stencil_status stencil_sync(void* stream);
 
 /* Diagnostic: average time of one device-wide synchronisation of a grid of
@@ -196,6 +201,45 @@ stencil_status stencil_sync(void* stream);
  * result, rounds above 1e6), STENCIL_ERR_TIMEOUT (a bounded wait expired),
  * device errors. */
 stencil_status stencil_probe_grid_sync(int32_t rounds, void* stream, double* seconds_per_sync);
+
+/* ---- Microbenchmarks for the model's parameters (paper Section 5.1: the
+ * bandwidths B_gm and B_sm; Section 6.1: latencies, whose product with a
+ * throughput is the parallelism a kernel needs by Little's law; Section
+ * 5.2.2: the cost of a synchronisation). Each allocates its own device
+ * memory stream-ordered on `stream`, times its kernels with events on it,
+ * synchronises it and releases the memory before returning. Errors:
+ * STENCIL_ERR_INVALID (arguments), STENCIL_ERR_NOMEM, STENCIL_ERR_DEVICE,
+ * STENCIL_ERR_TIMEOUT (a bounded wait of the neighbour probe expired). ----
+ *
+ * stencil_probe_copy: reachable HBM bandwidth, (read + write bytes) / s of a
+ *   streaming device copy of `bytes` (1 MiB .. 64 GiB; 2 x bytes allocated)
+ *   with 128-bit non-temporal loads and stores, best of five timed runs.
+ * stencil_probe_latency: seconds per link of a dependent chain, one lane:
+ *   STENCIL_PROBE_HBM_LATENCY loads that jump across a 1 GiB buffer (beyond
+ *   the last-level cache), STENCIL_PROBE_LDS_LATENCY loads from LDS,
+ *   STENCIL_PROBE_FMA64_LATENCY FP64 fused multiply-adds. The difference of
+ *   two chain lengths cancels the launch cost.
+ * stencil_probe_lds_bandwidth: bytes / s of conflict-free 128-bit LDS reads
+ *   over all CUs (two workgroups per CU).
+ * stencil_probe_neighbor_sync: one workgroup per CU on a 2D torus; in each of
+ *   `rounds` rounds a workgroup writes `payload_bytes` (0 .. 1 MiB), publishes
+ *   its round counter, waits for its four neighbours' counters (bounded by a
+ *   5 s watchdog) and reads their payloads. mode 0 publishes with an
+ *   agent-scope release (a write-back of the L2) and polls with acquires;
+ *   mode 1 writes the payload through to the coherence point, waits for those
+ *   stores and publishes with a plain counter store, the scheme of the 3D
+ *   device-tiled pass. *seconds_per_round is the average round; *mismatches
+ *   counts payload words read that did not carry their round's value (0 when
+ *   the publication scheme is sound). */
+#define STENCIL_PROBE_HBM_LATENCY 0
+#define STENCIL_PROBE_LDS_LATENCY 1
+#define STENCIL_PROBE_FMA64_LATENCY 2
+
+stencil_status stencil_probe_copy(int64_t bytes, void* stream, double* bytes_per_s);
+stencil_status stencil_probe_latency(int32_t kind, void* stream, double* seconds);
+stencil_status stencil_probe_lds_bandwidth(void* stream, double* bytes_per_s);
+stencil_status stencil_probe_neighbor_sync(int32_t mode, int32_t rounds, int32_t payload_bytes, void* stream,
+                                           double* seconds_per_round, uint64_t* mismatches);
 
 /* ---- Practical attainable performance model (paper Section 5, Section 6) ----
  *

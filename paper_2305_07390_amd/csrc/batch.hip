@@ -100,6 +100,14 @@ __global__ __launch_bounds__(64) void grid_sync_probe_kernel(unsigned int* ctr, 
   }
 }
 
+// Fold a launch's own error word into a report word read by stencil_sync.
+__global__ __launch_bounds__(64) void error_fold_kernel(const unsigned int* src, unsigned int* dst) {
+  if (threadIdx.x == 0) {
+    const unsigned v = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v != 0u) __hip_atomic_fetch_or(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 // blockIdx.y = job, blockIdx.x strides over the padded rows (z, y) of that job.
 template <typename Real>
 __global__ __launch_bounds__(64) void frame_copy_batch_kernel(const FrameCopyJob* __restrict__ jobs) {
@@ -130,6 +138,11 @@ hipError_t grid_sync_probe_launch(unsigned int* ctr, unsigned int* err, int roun
                                   long long timeout_ticks, hipStream_t stream) {
   hipLaunchKernelGGL(grid_sync_probe_kernel, dim3(grid), dim3(64), 0, stream, ctr, err, rounds,
                      timeout_ticks);
+  return hipGetLastError();
+}
+
+hipError_t error_fold_launch(const unsigned int* src, unsigned int* dst, hipStream_t stream) {
+  hipLaunchKernelGGL(error_fold_kernel, dim3(1), dim3(64), 0, stream, src, dst);
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -24,6 +25,18 @@ using namespace stencil_impl;
 namespace {
 
 constexpr int64_t kTimeoutTicks = 500000000;  // 5 s of the 100 MHz realtime clock
+
+// Watchdog limit of a launch's bounded waits: 5 s, or STENCIL_WATCHDOG_US
+// microseconds when that variable is set (tests shorten it to force expiry).
+int64_t timeout_ticks() {
+  const char* v = std::getenv("STENCIL_WATCHDOG_US");
+  if (v && *v) {
+    char* end = nullptr;
+    const long long us = std::strtoll(v, &end, 10);
+    if (end != v && us >= 0) return (int64_t)us * 100;  // 100 ticks per microsecond
+  }
+  return kTimeoutTicks;
+}
 // Batch tiles are longer than single-grid ones (fewer warm-up rows per tile),
 // but a job's passes run one after another, so a tile also bounds how fast
 // a long job can finish: measured on the 128-grid batch, 512 rows and 128
@@ -36,19 +49,25 @@ constexpr int kBatchSeg3D = 128;              // planes per 3D batch tile
 constexpr int kServeSeg2D = 256;
 constexpr int kServeSeg3D = 64;
 
-// Per-device error word shared by all batch launches on that device.
-unsigned int* device_error_word() {
+// Report word of a (device, stream): every launch on the stream has its own
+// error word, zeroed with its control block, which its kernels set when a
+// bounded wait expires; a small kernel after the launch ORs it into the
+// stream's report word, which only stencil_sync reads and clears. So an
+// expiry never leaks into another launch's waits, and each stream reports
+// its own.
+unsigned int* report_word(hipStream_t s) {
   static std::mutex mu;
-  static std::map<int, unsigned int*> words;
+  static std::map<std::pair<int, hipStream_t>, unsigned int*> words;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
   std::lock_guard<std::mutex> lock(mu);
-  auto it = words.find(dev);
+  const auto key = std::make_pair(dev, s);
+  auto it = words.find(key);
   if (it != words.end()) return it->second;
   unsigned int* w = nullptr;
   if (hipMalloc(&w, 256) != hipSuccess) return nullptr;
   if (hipMemset(w, 0, 256) != hipSuccess) return nullptr;
-  words[dev] = w;
+  words[key] = w;
   return w;
 }
 
@@ -289,6 +308,9 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     }
     m.lds = std::max(m.lds, (size_t)(4 * m.hq_stride) * elem);
   }
+  // this launch's own error word (zeroed with the control block)
+  const size_t err_off = total;
+  total = align256(total + sizeof(unsigned int));
   std::vector<FrameCopyJob> frames[2];  // per dtype
   for (int gi = 0; gi < 3; ++gi)
     for (int i : groups[gi].jobs) {
@@ -325,15 +347,16 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
                   hipGetErrorString(e));
     }
   }
-  unsigned int* err = device_error_word();
-  if (!err) {
+  unsigned int* report = report_word(s);
+  if (!report) {
     if (dev) hipFreeAsync(dev, s);
     return fail(STENCIL_ERR_NOMEM, "device error word allocation failed");
   }
+  unsigned int* err = (unsigned int*)(dev + err_off);
 
   // host image of the control region (everything after the workspaces is
   // small); counters start at zero
-  size_t ctl_lo = total;
+  size_t ctl_lo = std::min(total, err_off);
   for (int gi = 0; gi < 3; ++gi)
     if (!groups[gi].jobs.empty()) ctl_lo = std::min(ctl_lo, gmem[gi].jobs_off);
   for (int d = 0; d < 2; ++d) ctl_lo = std::min(ctl_lo, frames_off[d]);
@@ -400,7 +423,7 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     q.cursor = (unsigned long long*)(dev + m.cursor_off);
     q.done = (unsigned int*)(dev + m.done_off);
     q.err = err;
-    q.timeout_ticks = kTimeoutTicks;
+    q.timeout_ticks = timeout_ticks();
     // one workgroup per CU, never more than there are items
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cus, q.nitems));
     if (d == kF64) {
@@ -413,6 +436,11 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
                               : batch_launch(d, &prm, grid, m.lds, s);
     }
     if (e != hipSuccess) st = hip_fail(e, "batch launch");
+  }
+  // the launches' expiries go to the stream's report word
+  if (st == STENCIL_OK) {
+    e = error_fold_launch(err, report, s);
+    if (e != hipSuccess) st = hip_fail(e, "batch error report");
   }
   // jobs without a blocked variant: the plain path, workspace from the block
   for (int i : alone) {
@@ -543,22 +571,24 @@ stencil_status stencil_probe_grid_sync(int32_t rounds, void* stream, double* sec
     return fail(STENCIL_ERR_INVALID, "rounds in [1, 1e6] and a result pointer");
   *seconds_per_sync = 0;
   hipStream_t s = (hipStream_t)stream;
-  unsigned int* err = device_error_word();
-  if (!err) return fail(STENCIL_ERR_NOMEM, "device error word allocation failed");
+  unsigned int* report = report_word(s);
+  if (!report) return fail(STENCIL_ERR_NOMEM, "device error word allocation failed");
   DeviceInfo di = device_info();
   if (!di.ok) return fail(STENCIL_ERR_DEVICE, "no device");
   unsigned int* ctr = nullptr;
-  hipError_t e = hipMallocAsync((void**)&ctr, 256, s);
+  hipError_t e = hipMallocAsync((void**)&ctr, 512, s);
   if (e != hipSuccess) return hip_fail(e, "probe counter");
+  unsigned int* err = ctr + 64;  // the probe's own error word
   hipEvent_t e0 = nullptr, e1 = nullptr;
   stencil_status st = STENCIL_OK;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = fail(STENCIL_ERR_DEVICE, "events");
   // one launch to warm up, then the timed one
   for (int rep = 0; rep < 2 && st == STENCIL_OK; ++rep) {
-    e = hipMemsetAsync(ctr, 0, sizeof(unsigned int), s);
+    e = hipMemsetAsync(ctr, 0, 512, s);
     if (e == hipSuccess && rep == 1) e = hipEventRecord(e0, s);
-    if (e == hipSuccess) e = grid_sync_probe_launch(ctr, err, rounds, di.cus, kTimeoutTicks, s);
+    if (e == hipSuccess) e = grid_sync_probe_launch(ctr, err, rounds, di.cus, timeout_ticks(), s);
     if (e == hipSuccess && rep == 1) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = error_fold_launch(err, report, s);
     if (e != hipSuccess) st = hip_fail(e, "grid sync probe");
   }
   if (st == STENCIL_OK) st = stencil_sync(stream);
@@ -575,7 +605,7 @@ stencil_status stencil_probe_grid_sync(int32_t rounds, void* stream, double* sec
 
 stencil_status stencil_sync(void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  unsigned int* err = device_error_word();
+  unsigned int* err = report_word(s);
   PinnedWord* pw = err ? pinned_word() : nullptr;
   unsigned int h = 0;
   hipError_t e;
@@ -595,7 +625,9 @@ stencil_status stencil_sync(void* stream) {
     }
   }
   if (h) {
-    (void)hipMemset(err, 0, sizeof(unsigned int));
+    e = hipMemsetAsync(err, 0, sizeof(unsigned int), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "error word reset");
     return fail(STENCIL_ERR_TIMEOUT, "a bounded device wait expired; affected results are undefined");
   }
   return STENCIL_OK;

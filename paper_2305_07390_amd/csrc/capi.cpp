@@ -603,11 +603,12 @@ stencil_status stencil_run(const double* coeffs, int32_t radius, const stencil_s
   hipStream_t s = (hipStream_t)stream;
   void* ws = nullptr;
   if (plan->workspace) {
-    hipError_t e = hipMallocAsync(&ws, plan->workspace, s);
+    const size_t wbytes = plan->workspace;
+    hipError_t e = hipMallocAsync(&ws, wbytes, s);
     if (e != hipSuccess) {
       stencil_plan_destroy(plan);
-      return fail(STENCIL_ERR_NOMEM, "workspace allocation of %zu bytes failed: %s",
-                  plan->workspace, hipGetErrorString(e));
+      return fail(STENCIL_ERR_NOMEM, "workspace allocation of %zu bytes failed: %s", wbytes,
+                  hipGetErrorString(e));
     }
   }
   st = stencil_execute(plan, in, out, ws, stream);

@@ -131,6 +131,8 @@ hipError_t grid_sync_probe_launch(unsigned int* ctr, unsigned int* err, int roun
                                   long long timeout_ticks, hipStream_t stream);
 hipError_t frame_copy_batch_launch(int dtype, const FrameCopyJob* jobs_dev, int njobs,
                                    hipStream_t stream);
+// OR a launch's own error word into a report word (one small kernel on `stream`).
+hipError_t error_fold_launch(const unsigned int* src, unsigned int* dst, hipStream_t stream);
 
 // One step of the plain kernel, any ndim <= 3 (padded extents ext[0..2],
 // slowest first; unused leading extents are 1 with zero halo). The non-zero

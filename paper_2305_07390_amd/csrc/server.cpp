@@ -95,7 +95,7 @@ struct Request {
 struct stencil_server_s {
   stencil_server_config cfg;
   hipStream_t compute = nullptr, copy = nullptr, collect = nullptr;
-  hipEvent_t round_end = nullptr, inputs_ready = nullptr;
+  hipEvent_t round_end = nullptr, inputs_ready = nullptr, copy_mark = nullptr;
   std::mutex mu;
   std::condition_variable cv_work;  // new submissions or stop
   std::condition_variable cv_done;  // a request finished
@@ -170,8 +170,9 @@ void admit_locked(stencil_server_s* srv) {
     srv->st.admitted++;
     srv->resident.push_back(r);
     srv->pending_inputs = true;
+    // (a T = 0 request also runs in a round: its job is a device copy on the
+    // compute stream, ordered after the upload like every other job)
     r->state = RState::kResident;
-    if (r->remaining == 0) finish_locked(srv, r, RState::kDone, STENCIL_OK);  // T = 0: input is the result
   }
   int active = 0;
   for (Request* r : srv->resident) active += r->state == RState::kResident;
@@ -191,7 +192,6 @@ void scheduler(stencil_server_s* srv) {
       if (r->state == RState::kResident) round.push_back(r);
     if (round.empty()) {
       if (srv->stop) break;
-      srv->cv_done.notify_all();  // T = 0 requests admitted just now
       // Sleep until a queued request fits (a submission, or a collection
       // that frees a slot and memory). Waiting on "queue not empty" alone
       // would return at once while the head does not fit, and the loop would
@@ -251,6 +251,9 @@ void scheduler(stencil_server_s* srv) {
     }
     lock.unlock();
     if (st == STENCIL_OK) st = stencil_sync(srv->compute);
+    // a failed round may have left work queued: nothing of this round's
+    // requests is released before the compute stream is idle
+    if (st != STENCIL_OK) (void)hipStreamSynchronize(srv->compute);
     const double busy = std::chrono::duration<double>(Clock::now() - t0).count();
     lock.lock();
     srv->st.rounds++;
@@ -287,7 +290,13 @@ void release_locked(stencil_server_s* srv, Request* r) {
     srv->resident.erase(it);
     srv->st.hbm_in_use -= r->need;
   }
-  if (r->dev) (void)hipFreeAsync(r->dev, srv->collect);
+  if (r->dev) {
+    // the block may still be the target of an admission copy that no round
+    // waited for (a request that failed before its first round)
+    if (hipEventRecord(srv->copy_mark, srv->copy) == hipSuccess)
+      (void)hipStreamWaitEvent(srv->collect, srv->copy_mark, 0);
+    (void)hipFreeAsync(r->dev, srv->collect);
+  }
   r->dev = nullptr;
   if (r->host_in) {
     // the admission copy may still be in flight for a request that never ran
@@ -370,6 +379,7 @@ stencil_status stencil_server_create(const stencil_server_config* config, stenci
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->collect, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->round_end, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->inputs_ready, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->copy_mark, hipEventDisableTiming);
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     stencil_server_destroy(srv.release());
@@ -384,6 +394,8 @@ stencil_status stencil_server_create(const stencil_server_config* config, stenci
 stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* job, const void* host_in,
                                      uint64_t* ticket) {
   if (!srv || !job || !host_in || !ticket) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  // latency counts from the call, so planning and host staging are inside it
+  const Clock::time_point t_call = Clock::now();
   stencil_plan_t pl = nullptr;
   stencil_status st = stencil_plan(&pl, job->coeffs, job->radius, &job->shape, job->dtype, job->T, nullptr);
   if (st != STENCIL_OK) {
@@ -427,7 +439,7 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
   std::memcpy(r->host_in, host_in, r->bytes);
   std::lock_guard<std::mutex> lock(srv->mu);
   r->ticket = srv->next_ticket++;
-  r->t_submit = Clock::now();
+  r->t_submit = t_call;
   if (!srv->any_submit) {
     srv->any_submit = true;
     srv->first_submit = r->t_submit;
@@ -497,6 +509,7 @@ stencil_status stencil_server_destroy(stencil_server_t srv) {
   if (srv->collect) (void)hipStreamSynchronize(srv->collect);
   if (srv->round_end) (void)hipEventDestroy(srv->round_end);
   if (srv->inputs_ready) (void)hipEventDestroy(srv->inputs_ready);
+  if (srv->copy_mark) (void)hipEventDestroy(srv->copy_mark);
   if (srv->compute) (void)hipStreamDestroy(srv->compute);
   if (srv->copy) (void)hipStreamDestroy(srv->copy);
   if (srv->collect) (void)hipStreamDestroy(srv->collect);

@@ -56,14 +56,18 @@ def serve_open_loop(server: Server, requests, arrivals, keep_results: bool = Fal
     (seconds from the start, non-decreasing) from a submitter thread, and
     collect every result in submission order on the calling thread.
 
-    Returns ``{"latency_s": [...], "results": [...] or None, "rejected": [...],
-    "submit_lag_s": max lateness of a submission, "stats": server stats}``.
+    Returns ``{"latency_s": [...], "arrival_latency_s": [...], "results":
+    [...] or None, "rejected": [...], "submit_lag_s": max lateness of a
+    submission, "stats": server stats}``. ``latency_s`` is the server's own
+    figure (from the submit call to the end of the round that completes the
+    request); ``arrival_latency_s`` adds the request's lag from its scheduled
+    arrival to that call, so a driver that falls behind does not hide queueing.
     ``on_result(index, array)`` is called for each collected result."""
     n = len(requests)
     tickets = [None] * n
     errors = [None] * n
     ready = [threading.Event() for _ in range(n)]
-    lag = [0.0]
+    lags = [0.0] * n
     t0 = time.perf_counter()
 
     def submitter():
@@ -71,7 +75,7 @@ def serve_open_loop(server: Server, requests, arrivals, keep_results: bool = Fal
             delay = at - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
-            lag[0] = max(lag[0], time.perf_counter() - t0 - at)
+            lags[k] = max(0.0, time.perf_counter() - t0 - at)
             try:
                 tickets[k] = server.submit_problem(prob, field, T)
             except st.StencilError as e:
@@ -80,7 +84,7 @@ def serve_open_loop(server: Server, requests, arrivals, keep_results: bool = Fal
 
     th = threading.Thread(target=submitter, daemon=True)
     th.start()
-    latencies, results, rejected = [], [] if keep_results else None, []
+    latencies, arrival_lat, results, rejected = [], [], [] if keep_results else None, []
     for k in range(n):
         ready[k].wait()
         if tickets[k] is None:
@@ -89,10 +93,12 @@ def serve_open_loop(server: Server, requests, arrivals, keep_results: bool = Fal
         field = requests[k][1]
         out = np.empty_like(field)
         latencies.append(server.wait(tickets[k], out))
+        arrival_lat.append(latencies[-1] + lags[k])
         if keep_results:
             results.append(out)
         if on_result is not None:
             on_result(k, out)
     th.join()
-    return {"latency_s": latencies, "results": results, "rejected": rejected,
-            "submit_lag_s": lag[0], "stats": server.stats()}
+    return {"latency_s": latencies, "arrival_latency_s": arrival_lat, "results": results,
+            "rejected": rejected, "submit_lag_s": max(lags) if lags else 0.0,
+            "stats": server.stats()}

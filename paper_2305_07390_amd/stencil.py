@@ -151,6 +151,12 @@ _SIGNATURES = {
                                              ctypes.POINTER(ctypes.c_int)]),
     "stencil_sync": (ctypes.c_int, [_P]),
     "stencil_probe_grid_sync": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
+    "stencil_probe_copy": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_double)]),
+    "stencil_probe_latency": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
+    "stencil_probe_lds_bandwidth": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "stencil_probe_neighbor_sync": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                                                    ctypes.POINTER(ctypes.c_double),
+                                                    ctypes.POINTER(ctypes.c_uint64)]),
     "stencil_model_eval": (ctypes.c_int, [ctypes.POINTER(stencil_model_params),
                                            ctypes.POINTER(stencil_model_result)]),
     "stencil_tune": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape), ctypes.c_int,
@@ -238,6 +244,46 @@ def _dtype_code(dtype) -> int:
     raise ValueError(f"unsupported dtype {dtype}")
 
 
+def padded_nbytes(interior, radius: int, dtype) -> int:
+    """Bytes of one padded array (interior + 2r per axis) of `dtype`."""
+    n = 1
+    for v in interior:
+        n *= int(v) + 2 * int(radius)
+    return n * (8 if _dtype_code(dtype) == STENCIL_F64 else 4)
+
+
+def _check_tensor(name: str, x, dtype_code: int, nbytes: int):
+    """A device tensor handed to the library must be contiguous, of the plan's
+    dtype and exactly one padded array long: the kernels address it from the
+    plan's geometry, so anything smaller would be read or written out of
+    bounds."""
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if _dtype_code(x.dtype) != dtype_code:
+        raise ValueError(f"{name}: dtype {x.dtype} does not match the plan's "
+                         f"{'float64' if dtype_code == STENCIL_F64 else 'float32'}")
+    got = x.numel() * x.element_size()
+    if got != nbytes:
+        raise ValueError(f"{name}: {got} bytes, the plan needs one padded array of {nbytes} bytes")
+
+
+def _check_on_gpu(*named):
+    for name, x in named:
+        if x.device.type != "cuda":
+            raise ValueError(f"{name}: tensor must be on a GPU device")
+
+
+def _check_host(name: str, a: np.ndarray, dtype_code: int, nbytes: int, writable: bool = False):
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError(f"{name}: array must be C-contiguous")
+    if _dtype_code(a.dtype) != dtype_code:
+        raise ValueError(f"{name}: dtype {a.dtype} does not match the request's")
+    if a.nbytes != nbytes:
+        raise ValueError(f"{name}: {a.nbytes} bytes, the request needs one padded array of {nbytes} bytes")
+    if writable and not a.flags["WRITEABLE"]:
+        raise ValueError(f"{name}: array must be writable")
+
+
 def stencil_plan(coeffs, radius: int, interior, dtype, T: int, depth: int = 0, seg_len: int = 0,
                  flags: int = 0):
     """Create a plan; returns an opaque handle (int). Raises StencilError."""
@@ -304,6 +350,39 @@ def stencil_probe_grid_sync(rounds: int = 1000, stream: int = 0) -> float:
     out = ctypes.c_double()
     _check(load_library().stencil_probe_grid_sync(int(rounds), stream or None, ctypes.byref(out)))
     return out.value
+
+
+STENCIL_PROBE_HBM_LATENCY, STENCIL_PROBE_LDS_LATENCY, STENCIL_PROBE_FMA64_LATENCY = 0, 1, 2
+PROBE_HBM_LATENCY, PROBE_LDS_LATENCY, PROBE_FMA64_LATENCY = 0, 1, 2
+
+
+def stencil_probe_copy(nbytes: int = 2 << 30, stream: int = 0) -> float:
+    """Reachable HBM bandwidth (read + write bytes per second) of a streaming copy."""
+    out = ctypes.c_double()
+    _check(load_library().stencil_probe_copy(int(nbytes), stream or None, ctypes.byref(out)))
+    return out.value
+
+
+def stencil_probe_latency(kind: int, stream: int = 0) -> float:
+    """Seconds per link of a dependent chain (PROBE_* kinds)."""
+    out = ctypes.c_double()
+    _check(load_library().stencil_probe_latency(int(kind), stream or None, ctypes.byref(out)))
+    return out.value
+
+
+def stencil_probe_lds_bandwidth(stream: int = 0) -> float:
+    out = ctypes.c_double()
+    _check(load_library().stencil_probe_lds_bandwidth(stream or None, ctypes.byref(out)))
+    return out.value
+
+
+def stencil_probe_neighbor_sync(mode: int, rounds: int = 2000, payload_bytes: int = 0, stream: int = 0):
+    """(seconds per round, payload words that did not carry their round's value)."""
+    t = ctypes.c_double()
+    bad = ctypes.c_uint64()
+    _check(load_library().stencil_probe_neighbor_sync(int(mode), int(rounds), int(payload_bytes), stream or None,
+                                                      ctypes.byref(t), ctypes.byref(bad)))
+    return t.value, bad.value
 
 
 def stencil_sync(stream: int = 0):
@@ -387,29 +466,61 @@ def _job_struct(coeffs, radius, interior, dtype, T):
     return j, c
 
 
+# (server, ticket) -> (dtype code, padded bytes) of requests not yet collected,
+# so that a result is only ever copied into a host array of the right size
+_tickets = {}
+_tickets_lock = __import__("threading").Lock()
+
+
 def stencil_server_submit(server, coeffs, radius: int, interior, T: int, host_in: np.ndarray) -> int:
     """Submit one request; `host_in` is the padded input (its dtype is the
     request's). Returns the ticket."""
     a = np.ascontiguousarray(host_in)
+    code = _dtype_code(a.dtype)
+    nbytes = padded_nbytes(interior, radius, a.dtype)
+    _check_host("host_in", a, code, nbytes)
     j, keep = _job_struct(coeffs, radius, interior, a.dtype, T)
     t = ctypes.c_uint64()
     _check(load_library().stencil_server_submit(server, ctypes.byref(j), a.ctypes.data, ctypes.byref(t)))
+    with _tickets_lock:
+        _tickets[(server, t.value)] = (code, nbytes)
     return t.value
+
+
+def _out_ptr(server, ticket: int, host_out):
+    if host_out is None:
+        return None
+    with _tickets_lock:
+        meta = _tickets.get((server, int(ticket)))
+    if meta is None:
+        raise ValueError(f"unknown ticket {ticket}")
+    _check_host("host_out", host_out, meta[0], meta[1], writable=True)
+    return host_out.ctypes.data
+
+
+def _retire(server, ticket: int):
+    with _tickets_lock:
+        _tickets.pop((server, int(ticket)), None)
 
 
 def stencil_server_poll(server, ticket: int, host_out: np.ndarray | None = None):
     """(done, latency_s); when done the result is in host_out and the ticket is retired."""
     done = ctypes.c_int32()
     lat = ctypes.c_double()
-    ptr = host_out.ctypes.data if host_out is not None else None
-    _check(load_library().stencil_server_poll(server, int(ticket), ptr, ctypes.byref(done), ctypes.byref(lat)))
+    ptr = _out_ptr(server, ticket, host_out)
+    status = load_library().stencil_server_poll(server, int(ticket), ptr, ctypes.byref(done), ctypes.byref(lat))
+    if done.value or status != STENCIL_OK:
+        _retire(server, ticket)
+    _check(status)
     return bool(done.value), lat.value
 
 
 def stencil_server_wait(server, ticket: int, host_out: np.ndarray | None = None) -> float:
     lat = ctypes.c_double()
-    ptr = host_out.ctypes.data if host_out is not None else None
-    _check(load_library().stencil_server_wait(server, int(ticket), ptr, ctypes.byref(lat)))
+    ptr = _out_ptr(server, ticket, host_out)
+    status = load_library().stencil_server_wait(server, int(ticket), ptr, ctypes.byref(lat))
+    _retire(server, ticket)
+    _check(status)
     return lat.value
 
 
@@ -428,6 +539,11 @@ def run_batch(problems, xs, ys, stream=None, depth=0):
     `stream`; `problems` provide coefficients, radius and T."""
     specs = []
     for k, (prob, x, y) in enumerate(zip(problems, xs, ys)):
+        code = _dtype_code(x.dtype)
+        nbytes = padded_nbytes(prob.interior, prob.spec.r, x.dtype)
+        _check_tensor(f"job {k} input", x, code, nbytes)
+        _check_tensor(f"job {k} output", y, code, nbytes)
+        _check_on_gpu((f"job {k} input", x), (f"job {k} output", y))
         specs.append(dict(coeffs=prob.coeffs, radius=prob.spec.r, interior=prob.interior,
                           dtype=x.dtype, T=prob.T, in_ptr=x.data_ptr(), out_ptr=y.data_ptr(),
                           tag=getattr(prob, "tag", k), depth=depth))
@@ -474,7 +590,9 @@ class Plan:
 
     def __init__(self, coeffs, radius, interior, dtype, T, depth=0, seg_len=0, flags=0):
         self.handle = stencil_plan(coeffs, radius, interior, dtype, T, depth, seg_len, flags)
+        self.dtype_code = _dtype_code(dtype)
         self.radius = radius
+        self.flags = int(flags)
         self.interior = tuple(interior)
         self.T = T
         self.info = stencil_plan_describe(self.handle)
@@ -489,13 +607,26 @@ class Plan:
             self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
         return self._ws
 
+    @property
+    def persistent(self) -> bool:
+        return bool(self.flags & STENCIL_FLAG_PERSISTENT)
+
     def execute(self, x_in, x_out, stream=None):
-        """Run on torch device tensors (padded, contiguous). Enqueues on `stream`."""
-        if not (x_in.is_contiguous() and x_out.is_contiguous()):
-            raise ValueError("tensors must be contiguous")
+        """Run on torch device tensors (padded, contiguous, of the plan's dtype
+        and size). Enqueues on `stream`. A persistent plan's passes wait on
+        each other inside one launch; for it the call also waits for the
+        stream (stencil_sync), so that an expired bounded wait raises
+        StencilError(STENCIL_ERR_TIMEOUT) here instead of going unnoticed."""
+        nbytes = self.info["padded_bytes"]
+        _check_tensor("input", x_in, self.dtype_code, nbytes)
+        _check_tensor("output", x_out, self.dtype_code, nbytes)
+        _check_on_gpu(("input", x_in), ("output", x_out))
         ws = self.workspace(x_in.device)
+        sh = _stream_handle(stream)
         stencil_execute(self.handle, x_in.data_ptr(), x_out.data_ptr(),
-                        ws.data_ptr() if ws is not None else 0, _stream_handle(stream))
+                        ws.data_ptr() if ws is not None else 0, sh)
+        if self.persistent and self.info["scheme_name"] in ("blocked_2d", "blocked_3d"):
+            stencil_sync(sh)
         return x_out
 
     def close(self):
@@ -515,6 +646,11 @@ def run(coeffs, radius: int, x_in, T: int, x_out=None, stream=None):
     import torch
     if x_out is None:
         x_out = torch.empty_like(x_in)
+    code = _dtype_code(x_in.dtype)
+    nbytes = padded_nbytes(interior_of(x_in, radius), radius, x_in.dtype)
+    _check_tensor("input", x_in, code, nbytes)
+    _check_tensor("output", x_out, code, nbytes)
+    _check_on_gpu(("input", x_in), ("output", x_out))
     stencil_run(coeffs, radius, interior_of(x_in, radius), x_in.dtype, T, x_in.data_ptr(),
                 x_out.data_ptr(), _stream_handle(stream))
     return x_out

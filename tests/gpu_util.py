@@ -38,7 +38,8 @@ def gpu_sweep(coeffs, r, u0: np.ndarray, T: int, depth: int = 0, seg_len: int = 
     for _ in range(repeats):
         y = torch.full_like(x, float("nan"))
         plan.execute(x, y)
-        torch.cuda.synchronize()
+        # waits for the stream and raises if a bounded device wait expired
+        st.stencil_sync(st._stream_handle(None))
         outs.append(y.cpu().numpy())
     assert torch.equal(x, x_before), "input array was modified"
     for o in outs[1:]:

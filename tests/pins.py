@@ -236,6 +236,73 @@ def check_halo_fixed(sweep, ndim=3, kind="star", r=2, T=4, seed=31):
     assert np.array_equal(uT[mask], u0[mask])
 
 
+def round_f32(x) -> np.float32:
+    """The float32 nearest to the exact rational x, ties to an even significand
+    (IEEE 754 round-to-nearest-even), found among the neighbours of a first
+    guess by exact comparison (converting through float64 first could round
+    twice)."""
+    from fractions import Fraction
+    x = Fraction(x)
+    if x == 0:
+        return np.float32(0.0)
+    f = np.float32(float(x))
+    best = None
+    for c in (np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))):
+        if not np.isfinite(c):
+            continue
+        key = (abs(Fraction(float(c)) - x), int(np.array(c, dtype=np.float32).view(np.uint32)) & 1)
+        if best is None or key < best[0]:
+            best = (key, np.float32(c))
+    return best[1]
+
+
+def fmaf_exact(a, b, c) -> np.float32:
+    """a * b + c computed exactly and rounded once to float32."""
+    from fractions import Fraction
+    return round_f32(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
+
+
+def f32_reference(coeffs, r, u0, T):
+    """The float32 twin's definition on exact rationals: coefficients rounded
+    once to float32, each cell summed in dense-box order from +0 with one
+    rounding per term (a fused multiply-add), the halo held."""
+    ndim = u0.ndim
+    offs = [o for o in np.ndindex(*coeffs.shape) if coeffs[o] != 0.0]
+    w32 = [np.float32(coeffs[o]) for o in offs]
+    cur = u0.astype(np.float32).copy()
+    inner = [range(r, s - r) for s in u0.shape]
+    for _ in range(T):
+        nxt = cur.copy()
+        for idx in np.ndindex(*[len(x) for x in inner]):
+            cell = tuple(i + r for i in idx)
+            acc = np.float32(0.0)
+            for o, w in zip(offs, w32):
+                nb = tuple(c + oo - r for c, oo in zip(cell, o))
+                acc = fmaf_exact(w, cur[nb], acc)
+            nxt[cell] = acc
+        cur = nxt
+    return cur
+
+
+def check_f32_rounding(sweep, ndim=2, kind="box", r=1, T=3, seed=23):
+    """float32 sweep equals the exact-rational definition of one fused
+    multiply-add per term, bit for bit (random weights and values, so the
+    rounding of every term matters)."""
+    w = wl.random_coeffs(ndim, kind, r, seed)
+    interior = (4, 5) if ndim == 2 else (3, 4, 5)
+    u0 = wl.make_field(interior, r, seed, np.float32)
+    ref = f32_reference(w, r, u0, T)
+    got = sweep(w, r, u0, T)
+    assert got.dtype == np.float32
+    assert np.array_equal(got, ref), ("float32 rounding differs", np.max(np.abs(got.astype(np.float64) - ref)))
+
+
+F32_CHECKS = (
+    ("f32_exact_2d_box", lambda s: check_f32_rounding(s, 2, "box", 1)),
+    ("f32_exact_3d_star_r2", lambda s: check_f32_rounding(s, 3, "star", 2, T=2, seed=29)),
+)
+
+
 ALL_CHECKS = (
     ("constant_2d_star", lambda s: check_constant(s, 2, "star", 1)),
     ("constant_3d_box_r2", lambda s: check_constant(s, 3, "box", 2, T=3)),

@@ -22,6 +22,9 @@ pytestmark = pytest.mark.gpu
 U32 = 2.0 ** -24
 TS = (1, 10, 100)
 SHAPES = {2: (512, 640), 3: (64, 72, 80)}
+# the step counts of the workloads: T = 1000 (2D suite), T = 200 (3D suite),
+# up to 500 (batch and serving), on 1024^2 and 128^3 grids
+LONG = {2: ((1024, 1024), (500, 1000)), 3: ((128, 128, 128), (200, 500))}
 
 
 @pytest.mark.parametrize("spec", wl.ALL_STENCILS, ids=[s.name for s in wl.ALL_STENCILS])
@@ -43,5 +46,25 @@ def test_fp32_error_against_fp64_oracle(spec):
         bound = T * (k + 1) * U32 * umax
         rows.append({"stencil": spec.name, "T": T, "max_abs_err": err, "rel_to_max": err / umax,
                      "bound": bound})
+        assert err <= bound, rows[-1]
+    print(json.dumps(rows), flush=True)
+
+
+@pytest.mark.parametrize("spec", wl.ALL_STENCILS, ids=[s.name for s in wl.ALL_STENCILS])
+def test_fp32_error_at_workload_T(spec):
+    coeffs = wl.coeffs_for(spec, 500 + spec.r)
+    k = int(np.count_nonzero(coeffs))
+    shape, ts = LONG[spec.ndim]
+    u32 = wl.make_field(shape, spec.r, seed=93, dtype=np.float32)
+    u0 = u32.astype(np.float64)
+    umax = float(np.max(np.abs(u0)))
+    rows = []
+    for T in ts:
+        ref = oracle.sweep(coeffs, spec.r, u0, T)
+        got = gpu_sweep(coeffs, spec.r, u32, T).astype(np.float64)
+        err = float(np.max(np.abs(got - ref)))
+        bound = T * (k + 1) * U32 * umax
+        rows.append({"stencil": spec.name, "shape": list(shape), "T": T, "max_abs_err": err,
+                     "rel_to_max": err / umax, "bound": bound})
         assert err <= bound, rows[-1]
     print(json.dumps(rows), flush=True)

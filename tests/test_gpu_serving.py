@@ -110,3 +110,26 @@ def test_percentiles_match_latencies():
     assert s["p50_s"] == pytest.approx(rank(0.5), abs=1e-3)
     assert s["p99_s"] == pytest.approx(rank(0.99), abs=1e-3)
     assert s["cell_updates"] == sum(p.cells * T for p, _, T in reqs)
+
+
+def test_large_T0_request_returns_its_input():
+    """A T = 0 request runs as a device copy in a round, ordered after its
+    upload: a grid large enough that the upload takes a while comes back
+    unchanged."""
+    spec = wl.SUITE_2D[0]
+    coeffs = wl.coeffs_for(spec, 3)
+    f = wl.make_field((4096, 4096), 1, seed=71, dtype=np.float32)
+    g = wl.make_field((300, 400), 1, seed=72, dtype=np.float32)
+    with serving.Server(hbm_budget_bytes=4 << 30, max_slots=4, quantum_passes=1) as srv:
+        t0 = srv.submit(coeffs, 1, (4096, 4096), 0, f)
+        t1 = srv.submit(coeffs, 1, (300, 400), 5, g)
+        out0 = np.empty_like(f)
+        srv.wait(t0, out0)
+        out1 = np.empty_like(g)
+        srv.wait(t1, out1)
+    np.testing.assert_array_equal(out0, f)
+    np.testing.assert_array_equal(out1, _alone(spec_problem(spec, coeffs, (300, 400)), g, 5))
+
+
+def spec_problem(spec, coeffs, interior):
+    return wl.Problem(spec, coeffs, interior, 0, field_seed=0)

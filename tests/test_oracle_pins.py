@@ -17,6 +17,28 @@ def test_pin(name, check):
     check(_sweep)
 
 
+@pytest.mark.parametrize("name,check", pins.F32_CHECKS, ids=[n for n, _ in pins.F32_CHECKS])
+def test_f32_pin(name, check):
+    check(_sweep)
+
+
+def test_round_f32_ties_and_neighbours():
+    from fractions import Fraction
+    one = Fraction(1)
+    ulp = Fraction(1, 2 ** 23)
+    # exactly halfway between 1 and its successor: ties to the even significand (1)
+    assert pins.round_f32(one + ulp / 2) == np.float32(1.0)
+    # halfway between the successor and the next: ties to the even one above
+    assert pins.round_f32(one + ulp + ulp / 2) == np.float32(1.0) + np.float32(2 * 2.0 ** -23)
+    # a hair above halfway rounds up
+    assert pins.round_f32(one + ulp / 2 + Fraction(1, 2 ** 60)) == np.nextafter(np.float32(1), np.float32(2))
+    # a case where rounding through float64 first would round twice:
+    # 1 + 2^-24 + 2^-54 is above the tie, but its float64 is the tie itself
+    x = one + Fraction(1, 2 ** 24) + Fraction(1, 2 ** 54)
+    assert np.float32(float(x)) == np.float32(1.0)
+    assert pins.round_f32(x) == np.nextafter(np.float32(1), np.float32(2))
+
+
 def test_dyadic_f32_bitwise():
     # m + qT = 3 + 3*7 = 24 fits the float32 mantissa
     pins.check_dyadic(_sweep, 2, "star", 1, q=3, m=3, T=7, dtype=np.float32)
