@@ -14,6 +14,13 @@ namespace stencil_dev {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Wait until every vector-memory operation this wave has issued is complete
+// (gfx9 parts count loads and stores in one counter). A store written through
+// to the point of device coherence (an agent-scope atomic store) is visible to
+// every CU once it completes, so a flag stored after this wait never overtakes
+// the data it announces. A compiler barrier as well.
+__device__ __forceinline__ void wait_vmem_complete() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // Buffer descriptor word 3 for gfx9-family parts: 32-bit data format, raw
 // (untyped) addressing, range checking on num_records.
 constexpr int kRsrcWord3 = 0x00020000;

@@ -102,7 +102,9 @@ __global__ __launch_bounds__(256) void lds_bw_kernel(int iters, uint32_t* out) {
 // mode 0: plain stores, agent-scope release (writes back the L2) and an
 //         acquire poll (invalidates it), plain loads;
 // mode 1: payload written through to the coherence point (agent-scope relaxed
-//         stores), a wait for those stores, a relaxed counter store; relaxed
+//         stores), a wait in every wave until those stores are complete
+//         (without it the counter can become visible first: observed as
+//         stale payload words), a relaxed counter store; relaxed
 //         agent-scope polls and payload loads (they bypass the non-coherent
 //         caches). No whole-cache write-back.
 template <int MODE>
@@ -130,6 +132,9 @@ __global__ __launch_bounds__(256) void neighbor_sync_kernel(double* buf, unsigne
         __hip_atomic_store((unsigned long long*)(mine + i), __builtin_bit_cast(unsigned long long, (double)k),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // mode 1: each wave waits until its own write-through stores are complete
+    // before the barrier that precedes the counter store
+    if (MODE == 1) wait_vmem_complete();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (wave0) {
