@@ -149,6 +149,22 @@ stencil_status stencil_plan_destroy(stencil_plan_t plan);
 stencil_status stencil_run(const double* coeffs, int32_t radius, const stencil_shape* shape,
                            stencil_dtype dtype, int64_t T, const void* in, void* out, void* stream);
 
+/* For callers that cannot allocate device memory (work recorded under stream
+ * capture, tight serving loops, hosts that forbid allocation): stencil_run
+ * with the same arguments and results, bit for bit, that makes no device
+ * allocation or release. A plan of two or more passes uses, as its ping-pong
+ * workspace, a library-owned device region of STENCIL_NOALLOC_SCRATCH_BYTES
+ * (64 MiB), one per GPU, held from the first call on that GPU until the
+ * process ends. Plans whose workspace (one padded grid) is larger are
+ * rejected with STENCIL_ERR_INVALID and a message naming the limit; single-
+ * pass plans need no workspace and have no size limit. Calls that overlap on
+ * one GPU (two streams or threads at once) share the region and race: the
+ * caller serialises them. Other errors as stencil_run. */
+#define STENCIL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+stencil_status stencil_run_noalloc(const double* coeffs, int32_t radius, const stencil_shape* shape,
+                                   stencil_dtype dtype, int64_t T, const void* in, void* out,
+                                   void* stream);
+
 /* ---- Batched execution (many independent grids in persistent launches) ----
  *
  * A job is one stencil_run request: coefficients (host, copied at submit),

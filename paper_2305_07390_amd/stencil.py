@@ -147,6 +147,8 @@ _SIGNATURES = {
     "stencil_plan_destroy": (ctypes.c_int, [_P]),
     "stencil_run": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape),
                                     ctypes.c_int, ctypes.c_int64, _P, _P, _P]),
+    "stencil_run_noalloc": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape),
+                                            ctypes.c_int, ctypes.c_int64, _P, _P, _P]),
     "stencil_batch_submit": (ctypes.c_int, [ctypes.POINTER(stencil_job), ctypes.c_int32, _P,
                                              ctypes.POINTER(ctypes.c_int)]),
     "stencil_sync": (ctypes.c_int, [_P]),
@@ -571,6 +573,19 @@ def stencil_run(coeffs, radius: int, interior, dtype, T: int, in_ptr: int, out_p
     shp = _shape(interior)
     _check(lib.stencil_run(cp, int(radius), ctypes.byref(shp), _dtype_code(dtype), int(T), in_ptr,
                            out_ptr, stream or None))
+
+
+def stencil_run_noalloc(coeffs, radius: int, interior, dtype, T: int, in_ptr: int, out_ptr: int,
+                        stream: int = 0):
+    lib = load_library()
+    c, cp = _coeff_ptr(coeffs)
+    shp = _shape(interior)
+    _check(lib.stencil_run_noalloc(cp, int(radius), ctypes.byref(shp), _dtype_code(dtype), int(T), in_ptr,
+                                   out_ptr, stream or None))
+
+
+# Workspace limit of stencil_run_noalloc (include/stencil.h).
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 # --- torch conveniences -------------------------------------------------------

@@ -269,3 +269,16 @@ def test_python_constants_mirror_header_defines():
         if name.startswith("STENCIL_MODEL_"):
             continue  # exposed as MODEL_* in the binding
         assert getattr(st, name) == int(value), name
+
+
+def test_noalloc_rejects_workspace_beyond_region():
+    """A multi-pass plan whose workspace exceeds the no-alloc scratch region
+    is refused before any device work (so the pointers are never touched)."""
+    lib = _lib()
+    spec = wl.SUITE_2D[0]
+    c = np.ascontiguousarray(wl.coeffs_for(spec, 1), dtype=np.float64)
+    shp = st._shape((3000, 3000))  # 72 MB padded FP64, beyond 64 MiB
+    status = lib.stencil_run_noalloc(c.ctypes.data_as(st._DBL), 1, ctypes.byref(shp), st.STENCIL_F64, 100,
+                                     16, 32, None)
+    assert status == st.STENCIL_ERR_INVALID
+    assert b"scratch" in lib.stencil_last_error()
