@@ -78,7 +78,20 @@ typedef struct {
  *        also apply the Dirichlet columns and so cost more per row, are cut
  *        into shorter segments that take the wave slots the interior tiles
  *        leave free, so that no pass waits on them (batches set this flag:
- *        their jobs share the slots). */
+ *        their jobs share the slots);
+ *        STENCIL_FLAG_DEVICE_TILING asks a 3D plan for device tiling (paper
+ *        Section 4.1, "one tile at a time"): the interior xy plane is split
+ *        into 64 x 16 tiles without overlap, one workgroup each, all resident
+ *        at once (at most one per CU), every workgroup streams the whole z
+ *        extent through all levels and the tiles exchange their r-wide edges
+ *        of every level through global memory after each z-step, each tile
+ *        publishing one progress counter that its neighbours wait on
+ *        (bounded by the watchdog; stencil_sync reports an expiry). Applies
+ *        when x is a multiple of 64, y a multiple of 16, the tiles fit the
+ *        CUs, the padded grid is below 4 GiB, and the stencil is a radius-1
+ *        or radius-2 star or a radius-1 box; otherwise the plan falls back to
+ *        the overlapped tiles. STENCIL_FLAG_OVERLAPPED_TILING forbids device
+ *        tiling. Without either flag the planner chooses. */
 typedef struct {
   int32_t tile[3];
   int32_t depth;
@@ -89,13 +102,16 @@ typedef struct {
 #define STENCIL_FLAG_NO_CACHE 2
 #define STENCIL_FLAG_PERSISTENT 4
 #define STENCIL_FLAG_UNIFORM_TILES 8
+#define STENCIL_FLAG_DEVICE_TILING 16
+#define STENCIL_FLAG_OVERLAPPED_TILING 32
 
 /* Execution scheme chosen by a plan. */
 typedef enum {
   STENCIL_SCHEME_COPY = 0,       /* T = 0: out := in */
   STENCIL_SCHEME_NAIVE = 1,      /* one step per pass, no temporal blocking */
   STENCIL_SCHEME_BLOCKED_2D = 2, /* overlapped wave tiles streamed along y (tb2d) */
-  STENCIL_SCHEME_BLOCKED_3D = 3  /* overlapped 64x64 workgroup tiles streamed along z (tb3d) */
+  STENCIL_SCHEME_BLOCKED_3D = 3, /* overlapped 64x64 workgroup tiles streamed along z (tb3d) */
+  STENCIL_SCHEME_DEVICE_3D = 4   /* device tiling: 64x16 tiles exchanging edges every z-step (tb3d_dev) */
 } stencil_scheme;
 
 /* Pattern classes of the coefficient box. */

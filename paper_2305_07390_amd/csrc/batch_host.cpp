@@ -559,6 +559,11 @@ int serve_seg_3d() { return kServeSeg3D; }
 
 }  // namespace stencil_impl
 
+namespace stencil_impl {
+int64_t watchdog_ticks() { return timeout_ticks(); }
+unsigned int* stream_report_word(hipStream_t s) { return report_word(s); }
+}  // namespace stencil_impl
+
 extern "C" {
 
 stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* stream,

@@ -227,6 +227,36 @@ void plan_3d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
   p->grid = p->tiles;
 }
 
+// Device tiling (tb3d_dev) applies to this 3D plan at `depth`: tiles of
+// 64 x 16 interior cells cover the plane exactly, one per CU at most, and the
+// padded grid and the halo ring are addressable with 32-bit offsets.
+bool device_tiling_fits(const stencil_plan_s* p, int depth, int cus) {
+  const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
+  if (p->ndim != 3 || depth < 1 || depth > tb3d_dev_max_depth(dt, p->r, p->pattern)) return false;
+  const int ty = tb3d_dev_tile_y();
+  if (p->n[2] % 64 != 0 || p->n[1] % ty != 0) return false;
+  const int64_t tiles = (p->n[2] / 64) * (p->n[1] / ty);
+  if (tiles < 1 || tiles > cus) return false;
+  const int64_t grid_bytes = p->padded_elems * (int64_t)p->elem;
+  const int64_t ring_bytes = tiles * tb3d_dev_ring_elems(p->r, depth) * (int64_t)p->elem;
+  return grid_bytes < ((int64_t)1 << 32) && ring_bytes < ((int64_t)1 << 32);
+}
+
+// Device-tiled geometry and workspace layout: [ping-pong grid][halo ring]
+// [progress counters, error word].
+void plan_device_3d(stencil_plan_s* p, int depth) {
+  p->scheme = STENCIL_SCHEME_DEVICE_3D;
+  p->depth = depth;
+  p->sx = (int)(p->n[2] / 64);
+  p->sy = (int)(p->n[1] / tb3d_dev_tile_y());
+  p->hx = p->hy = 0;
+  p->seg_len = (int)p->ext[0];
+  p->segs = 1;
+  p->tiles = p->sx * p->sy;
+  p->grid = p->tiles;
+  p->block = 256;
+}
+
 stencil_status validate(const double* coeffs, int32_t radius, const stencil_shape* shape,
                         stencil_dtype dtype, int64_t T) {
   if (!coeffs) return fail(STENCIL_ERR_INVALID, "coeffs is NULL");
@@ -330,6 +360,59 @@ stencil_status run_blocked_3d(const stencil_plan_s* p, const void* in, void* out
     src = bufs[k % 2];
   }
   return STENCIL_OK;
+}
+
+// Device-tiled 3D passes: each pass is one launch of gx x gy workgroups (all
+// resident); the progress counters grow monotonically over the passes of one
+// execution (pass k starts from the sum of the earlier passes' iterations),
+// so no counter is reset between passes.
+template <typename Real>
+stencil_status run_device_3d(const stencil_plan_s* p, const void* in, void* out, void* ws,
+                             hipStream_t stream) {
+  const size_t npass = p->pass_depth.size();
+  char* wsb = (char*)ws;
+  void* grid2 = npass >= 2 ? ws : nullptr;
+  void* bufs[2];
+  if (npass % 2 == 1) { bufs[0] = out; bufs[1] = grid2; }
+  else { bufs[0] = grid2; bufs[1] = out; }
+  const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
+  unsigned int* report = stream_report_word(stream);
+  if (!report) return fail(STENCIL_ERR_NOMEM, "device error word allocation failed");
+  hipError_t e = frame_copy_launch(dt, in, out, p->ext, p->rad, stream);
+  if (e != hipSuccess) return hip_fail(e, "halo copy");
+  if (grid2) {
+    e = frame_copy_launch(dt, in, grid2, p->ext, p->rad, stream);
+    if (e != hipSuccess) return hip_fail(e, "halo copy");
+  }
+  unsigned int* ctl = (unsigned int*)(wsb + p->dev_ctl_off);
+  e = fill_zero_u32_launch(ctl, (int64_t)p->tiles + 1, stream);
+  if (e != hipSuccess) return hip_fail(e, "progress counter reset");
+  Tb3dDevParams<Real> prm;
+  std::memset(&prm, 0, sizeof(prm));
+  prm.ring = (Real*)(wsb + p->dev_ring_off);
+  prm.flags = ctl;
+  prm.err = ctl + p->tiles;
+  prm.P = p->ext[2];
+  prm.Qy = p->ext[1];
+  prm.Qz = p->ext[0];
+  prm.gx = p->sx;
+  prm.gy = p->sy;
+  prm.timeout_ticks = watchdog_ticks();
+  for (size_t i = 0; i < p->coeffs.size() && i < 125; ++i) prm.w[i] = (Real)p->coeffs[i];
+  const void* src = in;
+  uint32_t base = 0;
+  for (size_t k = 0; k < npass; ++k) {
+    prm.src = src;
+    prm.dst = bufs[k % 2];
+    prm.depth = p->pass_depth[k];
+    prm.flag_base = base;
+    e = tb3d_dev_launch(dt, p->r, p->pattern, p->depth, &prm, stream);
+    if (e != hipSuccess) return hip_fail(e, "device-tiled 3D pass launch");
+    base += (uint32_t)tb3d_dev_iterations(p->r, p->pass_depth[k], p->ext[0]);
+    src = bufs[k % 2];
+  }
+  e = error_fold_launch(prm.err, report, stream);
+  return e == hipSuccess ? STENCIL_OK : hip_fail(e, "device-tiled error report");
 }
 
 template <typename Real>
@@ -477,6 +560,18 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
         p->depth = depth;
         plan_3d_tiles(p, depth, hint ? hint->tile[0] : 0, cus);
       }
+      // device tiling when asked for and applicable
+      const bool want_dev = hint && (hint->flags & STENCIL_FLAG_DEVICE_TILING) &&
+                            !(hint->flags & STENCIL_FLAG_OVERLAPPED_TILING);
+      if (want_dev) {
+        DeviceInfo di = device_info();
+        const int cus = di.ok ? di.cus : 256;
+        const int dmax = tb3d_dev_max_depth(dtype == STENCIL_F64 ? kF64 : kF32, radius, p->pattern);
+        int ddepth = (hint->depth > 0) ? hint->depth : dmax;
+        if (ddepth > dmax) ddepth = dmax;
+        if ((int64_t)ddepth > T) ddepth = (int)T;
+        if (device_tiling_fits(p, ddepth, cus)) plan_device_3d(p, ddepth);
+      }
     }
     const bool want_persistent = hint && (hint->flags & STENCIL_FLAG_PERSISTENT);
     if (want_persistent &&
@@ -496,7 +591,8 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
         }
       }
     }
-    if (p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D) {
+    if (p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D ||
+        p->scheme == STENCIL_SCHEME_DEVICE_3D) {
       int64_t q = T / p->depth, rem = T % p->depth;
       p->pass_depth.assign((size_t)q, p->depth);
       if (rem) p->pass_depth.push_back((int)rem);
@@ -506,6 +602,13 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
   }
   const size_t bytes = (size_t)p->padded_elems * p->elem;
   p->workspace = p->pass_depth.size() >= 2 ? bytes : 0;
+  if (p->scheme == STENCIL_SCHEME_DEVICE_3D) {
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    p->dev_ring_off = align(p->workspace);
+    p->dev_ring_bytes = (size_t)p->tiles * (size_t)tb3d_dev_ring_elems(p->r, p->depth) * p->elem;
+    p->dev_ctl_off = align(p->dev_ring_off + p->dev_ring_bytes);
+    p->workspace = p->dev_ctl_off + align(((size_t)p->tiles + 1) * sizeof(unsigned int));
+  }
   if (p->scheme == STENCIL_SCHEME_NAIVE && p->tap_off.size() > (size_t)kMaxNaiveTaps) {
     delete p;
     return fail(STENCIL_ERR_UNSUPPORTED, "more than %d non-zero coefficients without a blocked kernel",
@@ -536,8 +639,12 @@ stencil_status stencil_plan_describe(stencil_plan_t plan, stencil_plan_info* inf
   info->edge_tiles = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? plan->edge_tiles : 0;
   info->cols_per_lane = plan->scheme == STENCIL_SCHEME_BLOCKED_2D ? tb2d_cols_per_lane(plan->dtype, plan->r, plan->pattern)
                         : plan->scheme == STENCIL_SCHEME_BLOCKED_3D ? 4 : 1;
-  info->redundant_lanes = plan->scheme == STENCIL_SCHEME_BLOCKED_3D ? plan->hx : plan->hl;
-  if (plan->scheme == STENCIL_SCHEME_BLOCKED_3D) info->strips = plan->sx * plan->sy;
+  info->redundant_lanes = plan->scheme == STENCIL_SCHEME_BLOCKED_3D ? plan->hx
+                          : plan->scheme == STENCIL_SCHEME_DEVICE_3D ? 0
+                                                                     : plan->hl;
+  if (plan->scheme == STENCIL_SCHEME_BLOCKED_3D || plan->scheme == STENCIL_SCHEME_DEVICE_3D)
+    info->strips = plan->sx * plan->sy;
+  if (plan->scheme == STENCIL_SCHEME_DEVICE_3D) info->cols_per_lane = 4;
   info->grid = plan->grid;
   info->block = plan->block;
   info->cells = plan->cells;
@@ -586,6 +693,10 @@ stencil_status stencil_execute(stencil_plan_t plan, const void* in, void* out, v
   if (plan->scheme == STENCIL_SCHEME_BLOCKED_3D) {
     return plan->dtype == STENCIL_F64 ? run_blocked_3d<double>(plan, in, out, workspace, s)
                                       : run_blocked_3d<float>(plan, in, out, workspace, s);
+  }
+  if (plan->scheme == STENCIL_SCHEME_DEVICE_3D) {
+    return plan->dtype == STENCIL_F64 ? run_device_3d<double>(plan, in, out, workspace, s)
+                                      : run_device_3d<float>(plan, in, out, workspace, s);
   }
   return plan->dtype == STENCIL_F64 ? run_naive<double>(plan, in, out, workspace, s)
                                     : run_naive<float>(plan, in, out, workspace, s);

@@ -54,6 +54,26 @@ struct Tb3dParams {
   Real w[kMaxBox3D > 125 ? 125 : kMaxBox3D];  // dense (2r+1)^3 box, r <= 2
 };
 
+// One pass of the device-tiled 3D kernel (tb3d_dev_impl.hpp): the interior xy
+// plane is cut into gx x gy non-overlapping 64 x 16 tiles, one workgroup each
+// (all resident at once); every workgroup streams all Qz planes through
+// `depth` levels and exchanges tile edges through `ring` (ring elements per
+// tile: tb3d_dev_ring_elems), publishing its progress in flags[tile] as
+// flag_base + completed iterations. A bounded wait that expires sets *err.
+template <typename Real>
+struct Tb3dDevParams {
+  const void* src;
+  void* dst;
+  Real* ring;
+  unsigned int* flags;
+  unsigned int* err;
+  int64_t P, Qy, Qz;
+  int32_t gx, gy, depth;
+  uint32_t flag_base;
+  int64_t timeout_ticks;
+  Real w[125];  // dense (2r+1)^3 box, r <= 2
+};
+
 // ---- batched persistent execution ----------------------------------------
 // A batch runs many independent grids in one persistent launch per dtype.
 // Work items are a workgroup's share of one (job, pass): a 3D tile, or up to
@@ -166,6 +186,18 @@ int tb3d_cells_y(int dtype, int r, int shape);
 hipError_t tb3d_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
                        hipStream_t stream);
 int tb3d_max_depth(int dtype, int r, int shape);
+
+// Device-tiled 3D passes: launch the kernel compiled for depth `cdepth` (the
+// plan's depth; params->depth may be smaller for a remainder pass).
+hipError_t tb3d_dev_launch(int dtype, int r, int shape, int cdepth, const void* params, hipStream_t stream);
+int tb3d_dev_max_depth(int dtype, int r, int shape);
+// Tile extent in y (x is 64), halo-ring elements per tile for a plan of
+// depth `cdepth`, and iterations of one pass of depth d over Qz planes.
+int tb3d_dev_tile_y();
+int64_t tb3d_dev_ring_elems(int r, int cdepth);
+int64_t tb3d_dev_iterations(int r, int d, int64_t Qz);
+// Zero n 32-bit words (a small kernel, so that it may be captured in graphs).
+hipError_t fill_zero_u32_launch(unsigned int* p, int64_t n, hipStream_t stream);
 
 // Copy the halo frame (width r[j] on axis j; ext slowest first, unused leading
 // axes have extent 1 and width 0) from src to dst.

@@ -59,7 +59,13 @@ stencil_status stencil_run_noalloc(const double* coeffs, int32_t radius, const s
                                    stencil_dtype dtype, int64_t T, const void* in, void* out, void* stream) {
   if (!in || !out) return stencil_impl::fail(STENCIL_ERR_INVALID, "in/out is NULL");
   stencil_plan_t plan = nullptr;
-  stencil_status st = stencil_plan(&plan, coeffs, radius, shape, dtype, T, nullptr);
+  // overlapped tiles only: a device-tiled plan reports bounded-wait expiries
+  // through a per-stream word that is allocated on a stream's first use
+  stencil_tuning hint;
+  hint.tile[0] = hint.tile[1] = hint.tile[2] = 0;
+  hint.depth = 0;
+  hint.flags = STENCIL_FLAG_OVERLAPPED_TILING;
+  stencil_status st = stencil_plan(&plan, coeffs, radius, shape, dtype, T, &hint);
   if (st != STENCIL_OK) return st;
   const size_t wbytes = plan->workspace;
   if (wbytes > kScratchBytes) {

@@ -33,6 +33,10 @@ stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stre
                                   stencil_status* per_job_status, int seg2d, int seg3d);
 int serve_seg_2d();
 int serve_seg_3d();
+// Watchdog limit of in-kernel bounded waits (s_memrealtime ticks), and the
+// per-stream report word that stencil_sync reads (batch_host.cpp).
+int64_t watchdog_ticks();
+unsigned int* stream_report_word(hipStream_t s);
 stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::vector<const void*>& ins,
                          const std::vector<void*>& outs, const std::vector<void*>& wsg, hipStream_t s);
 }  // namespace stencil_impl
@@ -68,6 +72,9 @@ struct stencil_plan_s {
   std::vector<int64_t> tap_off;
   std::vector<double> tap_w;
   bool persistent = false;  // all passes in one persistent launch
+  // device-tiled 3D plan: byte offsets of the halo ring and of the control
+  // words (progress counters, then the error word) in the workspace
+  size_t dev_ring_off = 0, dev_ring_bytes = 0, dev_ctl_off = 0;
   bool plan_ok_3d(int) const { return r <= 2; }
 };
 

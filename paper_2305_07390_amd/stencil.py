@@ -32,13 +32,15 @@ STENCIL_FLAG_NAIVE = 1
 STENCIL_FLAG_NO_CACHE = 2
 STENCIL_FLAG_PERSISTENT = 4
 STENCIL_FLAG_UNIFORM_TILES = 8
+STENCIL_FLAG_DEVICE_TILING = 16
+STENCIL_FLAG_OVERLAPPED_TILING = 32
 
 STENCIL_TUNE_BATCH = 1
 STENCIL_TUNE_FORCE = 2
 
 TUNE_CACHE_PATH = os.path.join(HERE, "tune_cache.json")
 
-SCHEME_NAMES = {0: "copy", 1: "naive", 2: "blocked_2d", 3: "blocked_3d"}
+SCHEME_NAMES = {0: "copy", 1: "naive", 2: "blocked_2d", 3: "blocked_3d", 4: "device_3d"}
 PATTERN_NAMES = {0: "star", 1: "box", 2: "general"}
 
 STATUS_NAMES = {
@@ -628,10 +630,11 @@ class Plan:
 
     def execute(self, x_in, x_out, stream=None):
         """Run on torch device tensors (padded, contiguous, of the plan's dtype
-        and size). Enqueues on `stream`. A persistent plan's passes wait on
-        each other inside one launch; for it the call also waits for the
-        stream (stencil_sync), so that an expired bounded wait raises
-        StencilError(STENCIL_ERR_TIMEOUT) here instead of going unnoticed."""
+        and size). Enqueues on `stream`. A persistent plan's passes, and a
+        device-tiled plan's tiles, wait on each other inside a launch; for
+        them the call also waits for the stream (stencil_sync), so that an
+        expired bounded wait raises StencilError(STENCIL_ERR_TIMEOUT) here
+        instead of going unnoticed."""
         nbytes = self.info["padded_bytes"]
         _check_tensor("input", x_in, self.dtype_code, nbytes)
         _check_tensor("output", x_out, self.dtype_code, nbytes)
@@ -640,7 +643,8 @@ class Plan:
         sh = _stream_handle(stream)
         stencil_execute(self.handle, x_in.data_ptr(), x_out.data_ptr(),
                         ws.data_ptr() if ws is not None else 0, sh)
-        if self.persistent and self.info["scheme_name"] in ("blocked_2d", "blocked_3d"):
+        if (self.persistent and self.info["scheme_name"] in ("blocked_2d", "blocked_3d")) or \
+                self.info["scheme_name"] == "device_3d":
             stencil_sync(sh)
         return x_out
 
