@@ -229,7 +229,8 @@ void plan_3d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus) {
 
 // Device tiling (tb3d_dev) applies to this 3D plan at `depth`: tiles of
 // 64 x 16 interior cells cover the plane exactly, one per CU at most, and the
-// padded grid and the halo ring are addressable with 32-bit offsets.
+// padded grid and the halo ring stay below 2 GiB (the kernel addresses them
+// with 32-bit offsets and uses offsets from 2 GiB up for dropped accesses).
 bool device_tiling_fits(const stencil_plan_s* p, int depth, int cus) {
   const int dt = p->dtype == STENCIL_F64 ? kF64 : kF32;
   if (p->ndim != 3 || depth < 1 || depth > tb3d_dev_max_depth(dt, p->r, p->pattern)) return false;
@@ -238,12 +239,12 @@ bool device_tiling_fits(const stencil_plan_s* p, int depth, int cus) {
   const int64_t tiles = (p->n[2] / 64) * (p->n[1] / ty);
   if (tiles < 1 || tiles > cus) return false;
   const int64_t grid_bytes = p->padded_elems * (int64_t)p->elem;
-  const int64_t ring_bytes = tiles * tb3d_dev_ring_elems(p->r, depth) * (int64_t)p->elem;
-  return grid_bytes < ((int64_t)1 << 32) && ring_bytes < ((int64_t)1 << 32);
+  const int64_t ring_bytes = tiles * tb3d_dev_ring_elems(p->r, depth) * 2 * (int64_t)p->elem;
+  return grid_bytes < ((int64_t)1 << 31) && ring_bytes < ((int64_t)1 << 31);
 }
 
 // Device-tiled geometry and workspace layout: [ping-pong grid][halo ring]
-// [progress counters, error word].
+// [error word].
 void plan_device_3d(stencil_plan_s* p, int depth) {
   p->scheme = STENCIL_SCHEME_DEVICE_3D;
   p->depth = depth;
@@ -363,9 +364,9 @@ stencil_status run_blocked_3d(const stencil_plan_s* p, const void* in, void* out
 }
 
 // Device-tiled 3D passes: each pass is one launch of gx x gy workgroups (all
-// resident); the progress counters grow monotonically over the passes of one
-// execution (pass k starts from the sum of the earlier passes' iterations),
-// so no counter is reset between passes.
+// resident). The halo ring is zeroed once per execution; the tags of its words
+// grow monotonically over the passes (pass k starts from the sum of the
+// earlier passes' iterations), so nothing is reset between passes.
 template <typename Real>
 stencil_status run_device_3d(const stencil_plan_s* p, const void* in, void* out, void* ws,
                              hipStream_t stream) {
@@ -385,13 +386,13 @@ stencil_status run_device_3d(const stencil_plan_s* p, const void* in, void* out,
     if (e != hipSuccess) return hip_fail(e, "halo copy");
   }
   unsigned int* ctl = (unsigned int*)(wsb + p->dev_ctl_off);
-  e = fill_zero_u32_launch(ctl, (int64_t)p->tiles + 1, stream);
-  if (e != hipSuccess) return hip_fail(e, "progress counter reset");
+  e = fill_zero_u32_launch((unsigned int*)(wsb + p->dev_ring_off), (int64_t)(p->dev_ring_bytes / 4), stream);
+  if (e == hipSuccess) e = fill_zero_u32_launch(ctl, 1, stream);
+  if (e != hipSuccess) return hip_fail(e, "halo ring reset");
   Tb3dDevParams<Real> prm;
   std::memset(&prm, 0, sizeof(prm));
-  prm.ring = (Real*)(wsb + p->dev_ring_off);
-  prm.flags = ctl;
-  prm.err = ctl + p->tiles;
+  prm.ring = wsb + p->dev_ring_off;
+  prm.err = ctl;
   prm.P = p->ext[2];
   prm.Qy = p->ext[1];
   prm.Qz = p->ext[0];
@@ -406,7 +407,7 @@ stencil_status run_device_3d(const stencil_plan_s* p, const void* in, void* out,
     prm.dst = bufs[k % 2];
     prm.depth = p->pass_depth[k];
     prm.flag_base = base;
-    e = tb3d_dev_launch(dt, p->r, p->pattern, p->depth, &prm, stream);
+    e = tb3d_dev_launch(dt, p->r, p->pattern, p->pass_depth[k], &prm, stream);
     if (e != hipSuccess) return hip_fail(e, "device-tiled 3D pass launch");
     base += (uint32_t)tb3d_dev_iterations(p->r, p->pass_depth[k], p->ext[0]);
     src = bufs[k % 2];
@@ -605,9 +606,10 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
   if (p->scheme == STENCIL_SCHEME_DEVICE_3D) {
     auto align = [](size_t v) { return (v + 255) / 256 * 256; };
     p->dev_ring_off = align(p->workspace);
-    p->dev_ring_bytes = (size_t)p->tiles * (size_t)tb3d_dev_ring_elems(p->r, p->depth) * p->elem;
+    // each ring cell is stored as (32-bit word, tag) pairs: twice its size
+    p->dev_ring_bytes = (size_t)p->tiles * (size_t)tb3d_dev_ring_elems(p->r, p->depth) * 2 * p->elem;
     p->dev_ctl_off = align(p->dev_ring_off + p->dev_ring_bytes);
-    p->workspace = p->dev_ctl_off + align(((size_t)p->tiles + 1) * sizeof(unsigned int));
+    p->workspace = p->dev_ctl_off + align(sizeof(unsigned int));
   }
   if (p->scheme == STENCIL_SCHEME_NAIVE && p->tap_off.size() > (size_t)kMaxNaiveTaps) {
     delete p;

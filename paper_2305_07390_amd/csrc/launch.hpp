@@ -57,15 +57,15 @@ struct Tb3dParams {
 // One pass of the device-tiled 3D kernel (tb3d_dev_impl.hpp): the interior xy
 // plane is cut into gx x gy non-overlapping 64 x 16 tiles, one workgroup each
 // (all resident at once); every workgroup streams all Qz planes through
-// `depth` levels and exchanges tile edges through `ring` (ring elements per
-// tile: tb3d_dev_ring_elems), publishing its progress in flags[tile] as
-// flag_base + completed iterations. A bounded wait that expires sets *err.
+// `depth` levels and exchanges tile edges through `ring` (tb3d_dev_ring_elems
+// cells per tile, each stored as (32-bit word, tag) pairs: 2 x sizeof(Real)
+// bytes), zeroed before the first pass; iteration i of the pass tags its
+// words flag_base + i + 1. A bounded wait that expires sets *err.
 template <typename Real>
 struct Tb3dDevParams {
   const void* src;
   void* dst;
-  Real* ring;
-  unsigned int* flags;
+  void* ring;
   unsigned int* err;
   int64_t P, Qy, Qz;
   int32_t gx, gy, depth;
@@ -187,8 +187,8 @@ hipError_t tb3d_launch(int dtype, int r, int shape, int depth, const void* param
                        hipStream_t stream);
 int tb3d_max_depth(int dtype, int r, int shape);
 
-// Device-tiled 3D passes: launch the kernel compiled for depth `cdepth` (the
-// plan's depth; params->depth may be smaller for a remainder pass).
+// Device-tiled 3D passes: launch the kernel compiled for depth `cdepth` (each
+// pass runs the variant of its own depth).
 hipError_t tb3d_dev_launch(int dtype, int r, int shape, int cdepth, const void* params, hipStream_t stream);
 int tb3d_dev_max_depth(int dtype, int r, int shape);
 // Tile extent in y (x is 64), halo-ring elements per tile for a plan of

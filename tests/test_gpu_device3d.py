@@ -57,5 +57,6 @@ def test_short_grid_and_many_passes():
 
 
 def test_512_cube_fp64():
-    info = _check(STAR1, (512, 512, 512), 20)
+    d = st.Plan(wl.coeffs_for(STAR1, 3), 1, (512, 512, 512), np.float64, 1000, flags=DEV).info["depth"]
+    info = _check(STAR1, (512, 512, 512), 2 * d + 1)
     assert info["strips"] == 256 and info["passes"] == 3
