@@ -136,6 +136,8 @@ typedef struct {
   int32_t edge_seg_len;  /* rows per segment of the two edge strips (2D) */
   int32_t edge_tiles;    /* tiles of the edge strips when they have their own
                             segments (2D), else 0 */
+  double model_cells_per_s; /* the model's predicted rate of a full-depth pass
+                               (valid cell-updates / s; 0 for plain schemes) */
 } stencil_plan_info;
 
 typedef struct stencil_plan_s* stencil_plan_t;
@@ -245,7 +247,9 @@ stencil_status stencil_probe_grid_sync(int32_t rounds, void* stream, double* sec
  *
  * stencil_probe_copy: reachable HBM bandwidth, (read + write bytes) / s of a
  *   streaming device copy of `bytes` (1 MiB .. 64 GiB; 2 x bytes allocated)
- *   with 128-bit non-temporal loads and stores, best of five timed runs.
+ *   with 128-bit loads and stores: the best run over four kernel variants
+ *   (4 or 8 loads in flight per lane, non-temporal or ordinary accesses) and
+ *   grids of 4 to 32 workgroups per CU, three timed runs each.
  * stencil_probe_latency: seconds per link of a dependent chain, one lane:
  *   STENCIL_PROBE_HBM_LATENCY loads that jump across a 1 GiB buffer (beyond
  *   the last-level cache), STENCIL_PROBE_LDS_LATENCY loads from LDS,
@@ -316,18 +320,60 @@ typedef struct {
 
 stencil_status stencil_model_eval(const stencil_model_params* params, stencil_model_result* result);
 
+/* ---- Machine parameters of the model and the model-driven planner ----
+ *
+ * A process-wide set of the model's inputs (paper Section 5.1: bandwidths and
+ * compute throughput; Section 5.2.2: synchronisation costs; Section 6.1:
+ * latencies). The defaults are MI355X values measured with the probes above:
+ * copy bandwidth, LDS bandwidth, device-wide barrier, neighbour-counter round,
+ * chain latencies; the vector FP64 peak is 256 CUs x 4 SIMDs x 16 lanes x 2
+ * flops at the clock measured under the stencil kernels (2.15 GHz), and FP32
+ * runs at the same rate as built (packed FP32 is not used).
+ *
+ * Without a depth hint or an autotuner entry, stencil_plan chooses among the
+ * feasible candidates (2D: every compiled depth; 3D: every compiled depth of
+ * the overlapped tiles and, where it applies and is not forbidden, of device
+ * tiling) the one whose predicted rate is highest. The prediction
+ * (stencil_plan_info.model_cells_per_s) counts the candidate's own HBM
+ * traffic, LDS traffic and flops, redundant margin cells included (the valid
+ * proportion of Section 5.2.1), and for device tiling one neighbour
+ * synchronisation per z-step (Section 5.2.2); the desired depth of Section
+ * 6.2 and the deeper-versus-wider trade-off of Section 6.4 follow from
+ * maximising it.
+ *
+ * stencil_machine_get copies the current set; stencil_machine_set replaces it
+ * (NULL restores the defaults; STENCIL_ERR_INVALID for non-positive
+ * bandwidths, peaks or CU count, or negative sync times);
+ * stencil_machine_calibrate runs the probes on `stream` (synchronising it),
+ * stores the measured values and returns the new set in *out (may be NULL). */
+typedef struct {
+  double hbm_bytes_per_s;  /* B_gm: streaming copy (read + write bytes / s) */
+  double lds_bytes_per_s;  /* B_sm: LDS reads over all CUs */
+  double fp64_flops;       /* vector FP64 FMA peak (flop/s) */
+  double fp32_flops;       /* vector FP32 FMA peak as built (flop/s) */
+  double grid_sync_s;      /* T_Dsync: one device-wide barrier */
+  double neighbor_sync_s;  /* one neighbour-counter round of the device-tiled exchange */
+  double hbm_latency_s, lds_latency_s, fma_latency_s; /* dependent-chain latencies */
+  int32_t cus;             /* compute units */
+} stencil_machine;
+
+stencil_status stencil_machine_get(stencil_machine* out);
+stencil_status stencil_machine_set(const stencil_machine* m);
+stencil_status stencil_machine_calibrate(void* stream, stencil_machine* out);
+
 /* ---- Autotuner (paper Section 3.4: empirical depth search; Sections 5-6:
  * the model prunes) ----
  *
- * stencil_tune times candidate (depth, segment) pairs of the blocked kernel
- * for this stencil class and grid shape on `stream` and stores the fastest in
- * a process-wide cache keyed by (gfx arch, CU count, ndim, pattern class,
- * radius, points, dtype, half-octave size bucket per axis, single or batched).
- * Candidates: every compiled depth, each with the planner's segment for it and
- * (single grids) half and double that; candidates whose model rate (cells/s
- * of valid output, stencil_model_eval with HBM 8 TB/s, one read and one write
- * per cell and pass, 2k flops per cell and step) is below 60% of the best
- * model rate are not timed. STENCIL_TUNE_BATCH tunes the depth used by
+ * stencil_tune times candidate (scheme, depth, segment) plans of the blocked
+ * kernels for this stencil class and grid shape on `stream` and stores the
+ * fastest in a process-wide cache keyed by (gfx arch, CU count, ndim, pattern
+ * class, radius, points, dtype, half-octave size bucket per axis, single or
+ * batched). Candidates: every compiled depth, each with the planner's segment
+ * for it and (single grids) half and double that; for single 3D grids also
+ * every depth of device tiling where it applies. Candidates whose model rate
+ * (stencil_plan_info.model_cells_per_s: the plan's own traffic, flops and
+ * valid proportion under the current stencil_machine parameters) is below 60%
+ * of the best model rate are not timed. STENCIL_TUNE_BATCH tunes the depth used by
  * stencil_batch_submit, timing a batch of replicas of the grid that fills the
  * device; STENCIL_TUNE_FORCE re-measures a cached entry. The tuner allocates
  * and frees its own device buffers (in, out(s), workspace of the padded size)
@@ -335,8 +381,10 @@ stencil_status stencil_model_eval(const stencil_model_params* params, stencil_mo
  * exact). Errors: STENCIL_ERR_INVALID (arguments), STENCIL_ERR_UNSUPPORTED (no
  * blocked kernel for this stencil and shape), STENCIL_ERR_NOMEM, device errors.
  *
- * Plans without a hint and batch jobs with depth 0 use the cached choice.
- * stencil_tune_lookup reports it (found = 0 when absent); the cache is saved
+ * Plans without a hint and batch jobs with depth 0 use the cached choice
+ * (depth, segment and, for 3D, scheme; a caller's scheme flag wins).
+ * stencil_tune_lookup reports it in out->depth, out->tile[0] and out->flags
+ * (found = 0 when absent); the cache is saved
  * to and merged from a JSON file ({"entries": [{"key", "depth", "seg", ...}]});
  * stencil_tune_cache_key writes the key of a request into buf. */
 #define STENCIL_TUNE_BATCH 1
@@ -349,6 +397,8 @@ typedef struct {
   double model_cells_per_s; /* model rate of the chosen candidate */
   int32_t candidates;       /* candidates timed */
   int32_t from_cache;       /* 1 if answered from the cache */
+  int32_t flags;            /* chosen scheme: STENCIL_FLAG_DEVICE_TILING or
+                               STENCIL_FLAG_OVERLAPPED_TILING (3D), else 0 */
 } stencil_tune_result;
 
 stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_shape* shape,

@@ -86,23 +86,6 @@ bool classify(int ndim, int r, const double* c, int* pattern, int* points) {
   return true;
 }
 
-// Temporal depth chosen without tuning data: deep enough to move the bound off
-// HBM (paper Section 6.2) within the compiled variants; the values are the
-// fastest depths measured on 8192^2 FP64 grids.
-int default_depth_2d(int r, int pattern, int dtype) {
-  const int maxd = tb2d_max_depth(dtype, r, pattern);
-  const bool f64 = dtype == STENCIL_F64;
-  int d;
-  // measured fastest on 8192^2 (radius-2 stars stop short of their deepest
-  // variant, whose register rings crowd the file); the FP32 5-point star
-  // keeps 12: depth 10 is 2 % faster on one large grid, but its extra passes
-  // lengthen serving rounds (p50 33 -> 48 ms)
-  if (pattern == STENCIL_STAR) d = r == 1 ? 12 : r == 2 ? (f64 ? 7 : 6) : r == 3 ? 4 : 2;
-  else if (pattern == STENCIL_BOX) d = r == 1 ? 8 : r == 2 ? 5 : r == 3 ? 3 : 2;
-  else d = maxd;
-  return std::min(d, maxd);
-}
-
 void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus, bool edge_split) {
   const int V = tb2d_cols_per_lane(p->dtype, p->r, p->pattern);
   const int W = kWave * V;
@@ -167,10 +150,6 @@ void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus, bool edg
   p->block = 256;
   p->grid = (p->tiles + 3) / 4;
 }
-
-// Temporal depth for the 3D pass: the deepest compiled variant (the pass is
-// HBM-bound at every depth the registers allow).
-int default_depth_3d(int r, int pattern, int dtype) { return tb3d_max_depth(dtype, r, pattern); }
 
 // Redundant lanes per side of a 3D tile along an axis with B cells per lane.
 int halo_lanes_3d(int depth, int r, int B) { return (depth * r + B - 1) / B; }
@@ -514,11 +493,14 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
   const bool use_cache = !(hint && (hint->flags & STENCIL_FLAG_NO_CACHE)) &&
                          !(hint && (hint->depth > 0 || hint->tile[0] > 0));
   if (use_cache && T > 0) {
-    int d = 0, seg = 0;
-    if (tune_lookup_plan(p, false, &d, &seg)) {
+    int d = 0, seg = 0, sfl = 0;
+    if (tune_lookup_plan(p, false, &d, &seg, &sfl)) {
       tuned.depth = d;
       tuned.tile[0] = seg;
-      tuned.flags = hint ? hint->flags : 0;
+      // the measured scheme, unless the caller forbade or required one
+      const int caller = hint ? hint->flags : 0;
+      const int scheme_bits = STENCIL_FLAG_DEVICE_TILING | STENCIL_FLAG_OVERLAPPED_TILING;
+      tuned.flags = (caller & scheme_bits) ? caller : (caller | sfl);
       hint = &tuned;
     }
   }
@@ -528,51 +510,92 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
   } else {
     p->scheme = STENCIL_SCHEME_NAIVE;
     p->depth = 1;
+    DeviceInfo di = device_info();
+    const int cus = di.ok ? di.cus : machine().cus;
+    const int dt = dtype == STENCIL_F64 ? kF64 : kF32;
+    const int hint_depth = hint ? hint->depth : 0;
+    const int hint_seg = hint ? hint->tile[0] : 0;
+    const int hflags = hint ? hint->flags : 0;
+    // Candidates are the feasible (scheme, depth) pairs; a depth hint fixes the
+    // depth, otherwise the model's predicted rate decides (paper Sections 5-6).
+    // The model resolves rates to a few percent and leaves out per-pass costs
+    // (launches, halo-frame copies, a serving round's quantum of passes), so
+    // among the candidates within 3% of the best prediction the deepest (the
+    // fewest passes) wins.
+    std::vector<std::pair<double, stencil_plan_s>> cands;
+    auto consider = [&](const stencil_plan_s& c) { cands.emplace_back(plan_model_rate(&c), c); };
     if (!force_naive && p->ndim == 2 && radius >= 1 && p->points > 0) {
       const int V = tb2d_cols_per_lane(dtype, radius, p->pattern);
       const int maxd = tb2d_max_depth(dtype, radius, p->pattern);
-      int depth = (hint && hint->depth > 0) ? hint->depth : default_depth_2d(radius, p->pattern, dtype);
-      if (depth > maxd) depth = maxd;
-      if ((int64_t)depth > T) depth = (int)T;
-      // every strip must lie inside the interior, and its edge redundancy fit in the wave
-      const int HL = (depth * radius + V - 1) / V;
-      if (maxd >= 1 && depth >= 1 && p->n[2] >= (int64_t)kWave * V && 2 * HL < kWave) {
-        DeviceInfo di = device_info();
-        const int cus = di.ok ? di.cus : 256;
-        p->scheme = STENCIL_SCHEME_BLOCKED_2D;
-        p->depth = depth;
-        plan_2d_tiles(p, depth, hint ? hint->tile[0] : 0, cus,
-                      !(hint && (hint->flags & STENCIL_FLAG_UNIFORM_TILES)));
+      int lo = 1, hi = maxd;
+      if (hint_depth > 0) lo = hi = std::min(hint_depth, maxd);
+      for (int depth = lo; depth <= hi && (int64_t)depth <= T; ++depth) {
+        // every strip must lie inside the interior, and its edge redundancy fit in the wave
+        const int HL = (depth * radius + V - 1) / V;
+        if (p->n[2] < (int64_t)kWave * V || 2 * HL >= kWave) continue;
+        stencil_plan_s c = *p;
+        c.scheme = STENCIL_SCHEME_BLOCKED_2D;
+        c.depth = depth;
+        plan_2d_tiles(&c, depth, hint_seg, cus, !(hflags & STENCIL_FLAG_UNIFORM_TILES));
+        consider(c);
+      }
+      if (hint_depth > 0 && cands.empty() && maxd >= 1 && T >= 1) {
+        // a hint deeper than T: the deepest feasible depth not above T
+        for (int depth = std::min<int64_t>(maxd, T); depth >= 1 && cands.empty(); --depth) {
+          const int HL = (depth * radius + V - 1) / V;
+          if (p->n[2] < (int64_t)kWave * V || 2 * HL >= kWave) continue;
+          stencil_plan_s c = *p;
+          c.scheme = STENCIL_SCHEME_BLOCKED_2D;
+          c.depth = depth;
+          plan_2d_tiles(&c, depth, hint_seg, cus, !(hflags & STENCIL_FLAG_UNIFORM_TILES));
+          consider(c);
+        }
       }
     }
     if (!force_naive && p->ndim == 3 && radius >= 1 && p->points > 0) {
-      const int maxd = tb3d_max_depth(dtype, radius, p->pattern);
-      int depth = (hint && hint->depth > 0) ? hint->depth : default_depth_3d(radius, p->pattern, dtype);
-      if (depth > maxd) depth = maxd;
-      if ((int64_t)depth > T) depth = (int)T;
-      const int by = tb3d_cells_y(dtype == STENCIL_F64 ? kF64 : kF32, radius, p->pattern);
-      const int hx = halo_lanes_3d(depth, radius, 4), hy = halo_lanes_3d(depth, radius, by);
-      // tiles of 64 x 16*by interior cells; each needs its redundant margins inside
-      if (maxd >= 1 && depth >= 1 && p->n[2] >= 64 && p->n[1] >= 16 * by && 2 * hx < 16 &&
-          2 * hy < 16 && p->plan_ok_3d(depth)) {
-        DeviceInfo di = device_info();
-        const int cus = di.ok ? di.cus : 256;
-        p->scheme = STENCIL_SCHEME_BLOCKED_3D;
-        p->depth = depth;
-        plan_3d_tiles(p, depth, hint ? hint->tile[0] : 0, cus);
+      const bool no_dev = (hflags & STENCIL_FLAG_OVERLAPPED_TILING) != 0;
+      const bool only_dev = (hflags & STENCIL_FLAG_DEVICE_TILING) != 0 && !no_dev;
+      const int by = tb3d_cells_y(dt, radius, p->pattern);
+      auto depths = [&](int maxd, int* lo, int* hi) {
+        *lo = 1;
+        *hi = (int)std::min<int64_t>(maxd, T);
+        if (hint_depth > 0) *lo = *hi = (int)std::min<int64_t>(std::min(hint_depth, maxd), T);
+      };
+      int lo, hi;
+      // device tiling: non-overlapping tiles exchanging edges every z-step
+      if (!no_dev) {
+        depths(tb3d_dev_max_depth(dt, radius, p->pattern), &lo, &hi);
+        for (int depth = lo; depth <= hi; ++depth) {
+          if (!device_tiling_fits(p, depth, cus)) continue;
+          stencil_plan_s c = *p;
+          plan_device_3d(&c, depth);
+          consider(c);
+        }
       }
-      // device tiling when asked for and applicable
-      const bool want_dev = hint && (hint->flags & STENCIL_FLAG_DEVICE_TILING) &&
-                            !(hint->flags & STENCIL_FLAG_OVERLAPPED_TILING);
-      if (want_dev) {
-        DeviceInfo di = device_info();
-        const int cus = di.ok ? di.cus : 256;
-        const int dmax = tb3d_dev_max_depth(dtype == STENCIL_F64 ? kF64 : kF32, radius, p->pattern);
-        int ddepth = (hint->depth > 0) ? hint->depth : dmax;
-        if (ddepth > dmax) ddepth = dmax;
-        if ((int64_t)ddepth > T) ddepth = (int)T;
-        if (device_tiling_fits(p, ddepth, cus)) plan_device_3d(p, ddepth);
+      // overlapped tiles (when device tiling was asked for, only if it does not apply)
+      if (!(only_dev && !cands.empty())) {
+        depths(tb3d_max_depth(dt, radius, p->pattern), &lo, &hi);
+        for (int depth = lo; depth <= hi; ++depth) {
+          // tiles of 64 x 16*by interior cells; each needs its redundant margins inside
+          const int hx = halo_lanes_3d(depth, radius, 4), hy = halo_lanes_3d(depth, radius, by);
+          if (!(p->n[2] >= 64 && p->n[1] >= 16 * by && 2 * hx < 16 && 2 * hy < 16 && p->plan_ok_3d(depth))) continue;
+          stencil_plan_s c = *p;
+          c.scheme = STENCIL_SCHEME_BLOCKED_3D;
+          c.depth = depth;
+          plan_3d_tiles(&c, depth, hint_seg, cus);
+          consider(c);
+        }
       }
+    }
+    if (!cands.empty()) {
+      double top = 0.0;
+      for (const auto& c : cands) top = std::max(top, c.first);
+      const stencil_plan_s* pick = nullptr;
+      for (const auto& c : cands)
+        if (c.first >= 0.97 * top && (!pick || c.second.depth > pick->depth ||
+                                      (c.second.depth == pick->depth && c.first > plan_model_rate(pick))))
+          pick = &c.second;
+      *p = *pick;
     }
     const bool want_persistent = hint && (hint->flags & STENCIL_FLAG_PERSISTENT);
     if (want_persistent &&
@@ -652,6 +675,7 @@ stencil_status stencil_plan_describe(stencil_plan_t plan, stencil_plan_info* inf
   info->cells = plan->cells;
   info->padded_bytes = plan->padded_elems * (int64_t)plan->elem;
   info->workspace_bytes = (int64_t)plan->workspace;
+  info->model_cells_per_s = plan_model_rate(plan);
   return STENCIL_OK;
 }
 

@@ -1,8 +1,9 @@
 // Practical attainable performance model (paper Section 5) and the design
 // rules derived from it (Section 6): desired depth, minimum 3D tile, valid
-// proportions of SM and device tiling. Host code; the planner uses it with
-// MI355X parameters, and its outputs are pinned against the numbers the paper
-// prints for an A100.
+// proportions of SM and device tiling. Host code; its outputs are pinned
+// against the numbers the paper prints for an A100. The planner and the
+// autotuner evaluate it for each candidate plan with the MI355X machine
+// parameters (machine.cpp).
 #include <algorithm>
 #include <cmath>
 #include <cstring>

@@ -26,13 +26,19 @@ DeviceInfo device_info();
 struct stencil_plan_s;
 namespace stencil_impl {
 // Autotuner cache lookup for a plan's stencil class and size (tune.cpp).
-bool tune_lookup_plan(const stencil_plan_s* pl, bool batched, int* depth, int* seg);
+// flags (may be NULL) receives the entry's scheme flags (3D: device or
+// overlapped tiling).
+bool tune_lookup_plan(const stencil_plan_s* pl, bool batched, int* depth, int* seg, int* flags = nullptr);
 // Prepared plans through the persistent batch kernel (batch_host.cpp).
 // stencil_batch_submit with explicit batch tile lengths (2D rows, 3D planes).
 stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stream,
                                   stencil_status* per_job_status, int seg2d, int seg3d);
 int serve_seg_2d();
 int serve_seg_3d();
+// The model's machine parameters and its predicted rate of a plan
+// (machine.cpp).
+stencil_machine machine();
+double plan_model_rate(const stencil_plan_s* p);
 // Watchdog limit of in-kernel bounded waits (s_memrealtime ticks), and the
 // per-stream report word that stencil_sync reads (batch_host.cpp).
 int64_t watchdog_ticks();

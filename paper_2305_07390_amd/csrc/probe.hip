@@ -4,7 +4,8 @@
 // the parallelism a kernel needs).
 //
 // * copy: a streaming device copy with 128-bit loads and stores, the
-//   reachable HBM bandwidth B_gm;
+//   reachable HBM bandwidth B_gm (the best of a few unroll depths, cache
+//   policies and grid sizes);
 // * chase: dependent-load chains through HBM (a chain that jumps across a
 //   buffer far larger than the last-level cache) and through LDS, and a chain
 //   of dependent FP64 fused multiply-adds: one lane, time per link;
@@ -25,22 +26,24 @@ namespace {
 using namespace stencil_dev;
 typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
 
+// U independent 16-byte loads per lane in flight, then their stores;
+// non-temporal (NT) or ordinary accesses.
+template <int U, bool NT>
 __global__ __launch_bounds__(256) void copy_kernel(const u32x4v* __restrict__ src, u32x4v* __restrict__ dst,
                                                    int64_t n16) {
-  // four independent 16-byte loads per lane in flight, then their stores
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    const u32x4v a = __builtin_nontemporal_load(src + i);
-    const u32x4v b = __builtin_nontemporal_load(src + i + stride);
-    const u32x4v c = __builtin_nontemporal_load(src + i + 2 * stride);
-    const u32x4v d = __builtin_nontemporal_load(src + i + 3 * stride);
-    __builtin_nontemporal_store(a, dst + i);
-    __builtin_nontemporal_store(b, dst + i + stride);
-    __builtin_nontemporal_store(c, dst + i + 2 * stride);
-    __builtin_nontemporal_store(d, dst + i + 3 * stride);
+  for (; i + (U - 1) * stride < n16; i += U * stride) {
+    u32x4v v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = NT ? __builtin_nontemporal_load(src + i + u * stride) : src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (NT) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+      else dst[i + u * stride] = v[u];
+    }
   }
-  for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 // Chain over n nodes spaced `stride` 32-bit words apart: node i points to
@@ -190,8 +193,18 @@ __global__ __launch_bounds__(256) void neighbor_sync_kernel(double* buf, unsigne
 
 }  // namespace
 
-hipError_t probe_copy_launch(const void* src, void* dst, int64_t bytes, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, s, (const u32x4v*)src, (u32x4v*)dst, bytes / 16);
+// variant: 0..3 = (4 loads, NT), (8, NT), (4, ordinary), (8, ordinary)
+hipError_t probe_copy_launch(const void* src, void* dst, int64_t bytes, int grid, int variant, hipStream_t s) {
+  const u32x4v* a = (const u32x4v*)src;
+  u32x4v* b = (u32x4v*)dst;
+  const int64_t n = bytes / 16;
+  switch (variant) {
+    case 0: hipLaunchKernelGGL((copy_kernel<4, true>), dim3(grid), dim3(256), 0, s, a, b, n); break;
+    case 1: hipLaunchKernelGGL((copy_kernel<8, true>), dim3(grid), dim3(256), 0, s, a, b, n); break;
+    case 2: hipLaunchKernelGGL((copy_kernel<4, false>), dim3(grid), dim3(256), 0, s, a, b, n); break;
+    case 3: hipLaunchKernelGGL((copy_kernel<8, false>), dim3(grid), dim3(256), 0, s, a, b, n); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@
 #include "plan.hpp"
 
 namespace stencil_impl {
-hipError_t probe_copy_launch(const void* src, void* dst, int64_t bytes, int grid, hipStream_t s);
+hipError_t probe_copy_launch(const void* src, void* dst, int64_t bytes, int grid, int variant, hipStream_t s);
 hipError_t probe_chain_init_launch(uint32_t* buf, uint32_t n, uint32_t stride, uint32_t a, hipStream_t s);
 hipError_t probe_chase_hbm_launch(const uint32_t* buf, uint32_t stride, int steps, uint32_t* out, hipStream_t s);
 hipError_t probe_chase_lds_launch(int steps, uint32_t a, uint32_t* out, hipStream_t s);
@@ -65,13 +65,18 @@ stencil_status stencil_probe_copy(int64_t bytes, void* stream, double* bytes_per
   stencil_status st = STENCIL_OK;
   e = hipMemsetAsync(buf, 1, (size_t)bytes, s);
   if (e != hipSuccess) st = hip_fail(e, "copy probe fill");
-  // enough workgroups for several waves per SIMD on every CU
-  const int grid = di.cus * 8;
+  // kernel variants x grids of 4 .. 32 workgroups per CU; each timed three
+  // times after a warm-up run, the best time over all
   double best = 1e30;
-  for (int rep = 0; rep < 6 && st == STENCIL_OK; ++rep) {
-    double t = 0;
-    st = time_on(s, [&] { return probe_copy_launch(buf, buf + bytes, bytes, grid, s); }, &t);
-    if (rep > 0) best = std::min(best, t);  // the first run warms up
+  for (int variant = 0; variant < 4 && st == STENCIL_OK; ++variant) {
+    for (int per_cu = 4; per_cu <= 32 && st == STENCIL_OK; per_cu *= 2) {
+      const int grid = di.cus * per_cu;
+      for (int rep = 0; rep < 4 && st == STENCIL_OK; ++rep) {
+        double t = 0;
+        st = time_on(s, [&] { return probe_copy_launch(buf, buf + bytes, bytes, grid, variant, s); }, &t);
+        if (rep > 0) best = std::min(best, t);
+      }
+    }
   }
   (void)hipFreeAsync(buf, s);
   (void)hipStreamSynchronize(s);

@@ -29,6 +29,7 @@ namespace {
 struct Entry {
   int depth = 0;
   int seg = 0;
+  int flags = 0;  // STENCIL_FLAG_DEVICE_TILING or _OVERLAPPED_TILING for 3D plans
   double sec_per_step = 0;
   int candidates = 0;
 };
@@ -79,40 +80,10 @@ stencil_status probe_plan(const double* coeffs, int32_t radius, const stencil_sh
   return stencil_plan(out, coeffs, radius, shape, dtype, 1, &h);
 }
 
-// Model prediction (cells/s of valid output) for one candidate: global
-// traffic of one read and one write per cell and pass, 2k flops per cell and
-// step, overlapped tiles losing depth*r cells on each tiled side.
-double model_rate(const stencil_plan_s* pl, int depth, int seg) {
-  const bool f64 = pl->dtype == STENCIL_F64;
-  stencil_model_params m;
-  std::memset(&m, 0, sizeof(m));
-  m.B_gm = 8.0e12;
-  m.thr_cmp = f64 ? 78.6e12 : 157.3e12;
-  m.cell_bytes = (double)pl->elem;
-  m.a_gm = 2.0;
-  m.a_cmp = 2.0 * pl->points;
-  const double cells = (double)pl->cells;
-  m.D_gm = m.D_cmp = m.D_all = cells;
-  m.t = depth;
-  m.tiling = STENCIL_MODEL_SM_TILING;
-  m.rad = pl->r;
-  if (pl->ndim == 2) {
-    const int V = tb2d_cols_per_lane(pl->dtype, pl->r, pl->pattern);
-    m.tiled_dims = 2;
-    m.tile[0] = 64.0 * V;
-    m.tile[1] = seg + 2.0 * depth * pl->r;
-  } else {
-    m.tiled_dims = 2;
-    m.tile[0] = m.tile[1] = 64.0;
-  }
-  stencil_model_result r;
-  if (stencil_model_eval(&m, &r) != STENCIL_OK) return 0.0;
-  return r.PP;
-}
-
 struct Candidate {
-  int depth, seg;
-  double model;
+  int depth, seg, flags;
+  double model;  // plan_model_rate of the candidate plan (cells/s of valid output)
+  size_t workspace;
 };
 
 // Device buffers for timing runs.
@@ -166,13 +137,14 @@ namespace stencil_impl {
 
 // Cached choice for a plan about to be made, if any (used by stencil_plan and
 // stencil_batch_submit).
-bool tune_lookup_plan(const stencil_plan_s* pl, bool batched, int* depth, int* seg) {
+bool tune_lookup_plan(const stencil_plan_s* pl, bool batched, int* depth, int* seg, int* flags) {
   const std::string key = make_key(pl, batched);
   std::lock_guard<std::mutex> lock(g_mu);
   auto it = g_cache.find(key);
   if (it == g_cache.end()) return false;
   *depth = it->second.depth;
   *seg = it->second.seg;
+  if (flags) *flags = it->second.flags;
   return true;
 }
 
@@ -198,6 +170,7 @@ stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_
       result->seg_len = it->second.seg;
       result->seconds_per_step = it->second.sec_per_step;
       result->candidates = it->second.candidates;
+      result->flags = it->second.flags;
       result->from_cache = 1;
       stencil_plan_destroy(base);
       return STENCIL_OK;
@@ -205,38 +178,53 @@ stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_
   }
   const int scheme = base->scheme;
   const int ndim = base->ndim;
-  if (scheme != STENCIL_SCHEME_BLOCKED_2D && scheme != STENCIL_SCHEME_BLOCKED_3D) {
+  if (scheme != STENCIL_SCHEME_BLOCKED_2D && scheme != STENCIL_SCHEME_BLOCKED_3D &&
+      scheme != STENCIL_SCHEME_DEVICE_3D) {
     stencil_plan_destroy(base);
     return fail(STENCIL_ERR_UNSUPPORTED, "no blocked kernel for this stencil and shape: nothing to tune");
   }
-  const int maxd = ndim == 2 ? tb2d_max_depth(dtype, radius, base->pattern)
-                             : tb3d_max_depth(dtype, radius, base->pattern);
+  const int dt = dtype == STENCIL_F64 ? kF64 : kF32;
 
-  // Candidates: every compiled depth with the planner's segment for it, plus
-  // half and double that segment (single-grid tuning; batched tiles keep the
-  // batch segment). The model prunes depths predicted below 60% of its best.
+  // Candidates: every compiled depth of every applicable scheme (3D: the
+  // overlapped tiles and, single grids only, device tiling), each with the
+  // planner's segment for it and (single grids, overlapped tiles) half and
+  // double that segment; batched tiles keep the batch segment. The model
+  // (plan_model_rate with the machine parameters) prunes candidates predicted
+  // below 60% of its best; measurement decides among the rest.
   std::vector<Candidate> cand;
   double best_model = 0;
-  for (int d = 1; d <= maxd; ++d) {
+  auto add = [&](int d, int seg, int fl) {
     stencil_tuning h;
     std::memset(&h, 0, sizeof(h));
     h.depth = d;
-    h.flags = STENCIL_FLAG_NO_CACHE;
+    h.tile[0] = seg;
+    h.flags = STENCIL_FLAG_NO_CACHE | fl;
     stencil_plan_t p = nullptr;
-    if (stencil_plan(&p, coeffs, radius, shape, dtype, 4 * (int64_t)d, &h) != STENCIL_OK) continue;
-    if (p->scheme == scheme && p->depth == d) {
-      const int seg0 = p->seg_len;
-      const double m = model_rate(p, d, seg0);
+    if (stencil_plan(&p, coeffs, radius, shape, dtype, 4 * (int64_t)d, &h) != STENCIL_OK) return -1;
+    int got = -1;
+    const bool want_dev = (fl & STENCIL_FLAG_DEVICE_TILING) != 0;
+    const bool is_dev = p->scheme == STENCIL_SCHEME_DEVICE_3D;
+    if (p->depth == d && p->scheme != STENCIL_SCHEME_NAIVE && want_dev == is_dev) {
+      const double m = plan_model_rate(p);
       best_model = std::max(best_model, m);
-      cand.push_back({d, batched ? 0 : seg0, m});
-      if (!batched) {
-        const int lo = seg0 / 2, hi = seg0 * 2;
-        if (lo >= 8) cand.push_back({d, lo, model_rate(p, d, lo)});
-        if (hi <= (ndim == 2 ? p->n[1] : p->n[0])) cand.push_back({d, hi, model_rate(p, d, hi)});
-      }
+      cand.push_back({d, batched ? 0 : p->seg_len, fl, m, p->workspace});
+      got = p->seg_len;
     }
     stencil_plan_destroy(p);
+    return got;
+  };
+  const int fl_ov = ndim == 3 ? STENCIL_FLAG_OVERLAPPED_TILING : 0;
+  const int maxd = ndim == 2 ? tb2d_max_depth(dt, radius, base->pattern) : tb3d_max_depth(dt, radius, base->pattern);
+  for (int d = 1; d <= maxd; ++d) {
+    const int seg0 = add(d, 0, fl_ov);
+    if (seg0 > 0 && !batched) {
+      const int lo = seg0 / 2, hi = seg0 * 2;
+      if (lo >= 8) add(d, lo, fl_ov);
+      if (hi <= (ndim == 2 ? base->n[1] : base->n[0])) add(d, hi, fl_ov);
+    }
   }
+  if (ndim == 3 && !batched)
+    for (int d = 1; d <= tb3d_dev_max_depth(dt, radius, base->pattern); ++d) add(d, 0, STENCIL_FLAG_DEVICE_TILING);
   stencil_plan_destroy(base);
   std::vector<Candidate> keep;
   for (const Candidate& c : cand)
@@ -275,8 +263,10 @@ stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_
   }
   void* ws = nullptr;
   if (!batched) {
-    ws = buf.alloc(bytes);
-    if (!ws) return fail(STENCIL_ERR_NOMEM, "tuning workspace (%zu bytes)", bytes);
+    size_t wbytes = bytes;
+    for (const Candidate& c : keep) wbytes = std::max(wbytes, c.workspace);
+    ws = buf.alloc(wbytes);
+    if (!ws) return fail(STENCIL_ERR_NOMEM, "tuning workspace (%zu bytes)", wbytes);
   }
 
   double best_t = INFINITY;
@@ -294,7 +284,7 @@ stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_
       std::memset(&h, 0, sizeof(h));
       h.depth = c.depth;
       h.tile[0] = c.seg;
-      h.flags = STENCIL_FLAG_NO_CACHE;
+      h.flags = STENCIL_FLAG_NO_CACHE | c.flags;
       stencil_plan_t p = nullptr;
       st = stencil_plan(&p, coeffs, radius, shape, dtype, Tp, &h);
       if (st != STENCIL_OK) return st;
@@ -328,6 +318,7 @@ stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_
   Entry e;
   e.depth = best.depth;
   e.seg = best.seg;
+  e.flags = best.flags;
   e.sec_per_step = best_t;
   e.candidates = measured;
   {
@@ -339,6 +330,7 @@ stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_
   result->seconds_per_step = e.sec_per_step;
   result->candidates = e.candidates;
   result->model_cells_per_s = best.model;
+  result->flags = e.flags;
   result->from_cache = 0;
   return STENCIL_OK;
 }
@@ -353,9 +345,11 @@ stencil_status stencil_tune_lookup(const double* coeffs, int32_t radius, const s
   stencil_status st = probe_plan(coeffs, radius, shape, dtype, &p);
   if (st != STENCIL_OK) return st;
   int depth = 0, seg = 0;
-  if (tune_lookup_plan(p, (flags & STENCIL_TUNE_BATCH) != 0, &depth, &seg)) {
+  int sflags = 0;
+  if (tune_lookup_plan(p, (flags & STENCIL_TUNE_BATCH) != 0, &depth, &seg, &sflags)) {
     out->depth = depth;
     out->tile[0] = seg;
+    out->flags = sflags;
     *found = 1;
   }
   stencil_plan_destroy(p);
@@ -376,9 +370,9 @@ stencil_status stencil_tune_cache_save(const char* path) {
   std::fprintf(f, "{\n  \"version\": 1,\n  \"entries\": [");
   bool first = true;
   for (const auto& kv : g_cache) {
-    std::fprintf(f, "%s\n    {\"key\": \"%s\", \"depth\": %d, \"seg\": %d, \"sec_per_step\": %.6e, "
-                    "\"candidates\": %d}",
-                 first ? "" : ",", kv.first.c_str(), kv.second.depth, kv.second.seg,
+    std::fprintf(f, "%s\n    {\"key\": \"%s\", \"depth\": %d, \"seg\": %d, \"flags\": %d, "
+                    "\"sec_per_step\": %.6e, \"candidates\": %d}",
+                 first ? "" : ",", kv.first.c_str(), kv.second.depth, kv.second.seg, kv.second.flags,
                  kv.second.sec_per_step, kv.second.candidates);
     first = false;
   }
@@ -426,13 +420,15 @@ stencil_status stencil_tune_cache_load(const char* path, int32_t* loaded) {
     if (k == std::string::npos || k2 == std::string::npos)
       return fail(STENCIL_ERR_INVALID, "%s: malformed key", path);
     Entry e;
-    double d = 0, s = 0, t = 0, c = 0;
+    double d = 0, s = 0, t = 0, c = 0, fl = 0;
     if (!field_num(obj, "depth", &d) || !field_num(obj, "seg", &s) || d < 1 || d > 64 || s < 0)
       return fail(STENCIL_ERR_INVALID, "%s: entry needs depth >= 1 and seg >= 0", path);
     field_num(obj, "sec_per_step", &t);
     field_num(obj, "candidates", &c);
+    field_num(obj, "flags", &fl);
     e.depth = (int)d;
     e.seg = (int)s;
+    e.flags = (int)fl & (STENCIL_FLAG_DEVICE_TILING | STENCIL_FLAG_OVERLAPPED_TILING);
     e.sec_per_step = t;
     e.candidates = (int)c;
     parsed[obj.substr(k + 1, k2 - k - 1)] = e;

@@ -77,6 +77,7 @@ class stencil_plan_info(ctypes.Structure):
         ("grid", ctypes.c_int32), ("block", ctypes.c_int32), ("cells", ctypes.c_int64),
         ("padded_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
         ("edge_seg_len", ctypes.c_int32), ("edge_tiles", ctypes.c_int32),
+        ("model_cells_per_s", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -84,6 +85,14 @@ class stencil_plan_info(ctypes.Structure):
         d["scheme_name"] = SCHEME_NAMES.get(self.scheme, str(self.scheme))
         d["pattern_name"] = PATTERN_NAMES.get(self.pattern, str(self.pattern))
         return d
+
+
+class stencil_machine(ctypes.Structure):
+    _fields_ = [("hbm_bytes_per_s", ctypes.c_double), ("lds_bytes_per_s", ctypes.c_double),
+                ("fp64_flops", ctypes.c_double), ("fp32_flops", ctypes.c_double),
+                ("grid_sync_s", ctypes.c_double), ("neighbor_sync_s", ctypes.c_double),
+                ("hbm_latency_s", ctypes.c_double), ("lds_latency_s", ctypes.c_double),
+                ("fma_latency_s", ctypes.c_double), ("cus", ctypes.c_int32)]
 
 
 class stencil_job(ctypes.Structure):
@@ -113,7 +122,7 @@ class stencil_model_result(ctypes.Structure):
 class stencil_tune_result(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("seg_len", ctypes.c_int32),
                 ("seconds_per_step", ctypes.c_double), ("model_cells_per_s", ctypes.c_double),
-                ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+                ("candidates", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class stencil_server_config(ctypes.Structure):
@@ -163,6 +172,9 @@ _SIGNATURES = {
                                                     ctypes.POINTER(ctypes.c_uint64)]),
     "stencil_model_eval": (ctypes.c_int, [ctypes.POINTER(stencil_model_params),
                                            ctypes.POINTER(stencil_model_result)]),
+    "stencil_machine_get": (ctypes.c_int, [ctypes.POINTER(stencil_machine)]),
+    "stencil_machine_set": (ctypes.c_int, [ctypes.POINTER(stencil_machine)]),
+    "stencil_machine_calibrate": (ctypes.c_int, [_P, ctypes.POINTER(stencil_machine)]),
     "stencil_tune": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape), ctypes.c_int,
                                      ctypes.c_int32, _P, ctypes.POINTER(stencil_tune_result)]),
     "stencil_tune_lookup": (ctypes.c_int, [_DBL, ctypes.c_int32, ctypes.POINTER(stencil_shape),
@@ -566,6 +578,32 @@ def stencil_model_eval(**kw) -> dict:
     r = stencil_model_result()
     _check(load_library().stencil_model_eval(ctypes.byref(p), ctypes.byref(r)))
     return {name: getattr(r, name) for name, _ in r._fields_}
+
+
+def stencil_machine_get() -> dict:
+    m = stencil_machine()
+    _check(load_library().stencil_machine_get(ctypes.byref(m)))
+    return {name: getattr(m, name) for name, _ in m._fields_}
+
+
+def stencil_machine_set(params=None, **overrides):
+    """Replace the model's machine parameters (None and no overrides: the
+    defaults); keyword overrides apply on top of the current set."""
+    lib = load_library()
+    if params is None and not overrides:
+        _check(lib.stencil_machine_set(None))
+        return stencil_machine_get()
+    cur = dict(stencil_machine_get() if params is None else params)
+    cur.update(overrides)
+    m = stencil_machine(**cur)
+    _check(lib.stencil_machine_set(ctypes.byref(m)))
+    return stencil_machine_get()
+
+
+def stencil_machine_calibrate(stream: int = 0) -> dict:
+    m = stencil_machine()
+    _check(load_library().stencil_machine_calibrate(stream or None, ctypes.byref(m)))
+    return {name: getattr(m, name) for name, _ in m._fields_}
 
 
 def stencil_run(coeffs, radius: int, interior, dtype, T: int, in_ptr: int, out_ptr: int,

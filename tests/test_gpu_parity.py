@@ -82,20 +82,21 @@ def test_segment_invariance(seg):
     _check(w, 1, u0, 14, seg_len=seg, depth=7)
 
 
-@pytest.mark.parametrize("kind,r,interior,T,seg", [
-    ("star", 1, (450, 1300), 26, 100), ("box", 1, (611, 1333), 17, 150),
-    ("star", 3, (500, 1200), 9, 120), ("box", 2, (403, 1000), 11, 90),
-    ("star", 2, (700, 1500), 8, 1000)])
+@pytest.mark.parametrize("kind,r,interior,T,seg,depth", [
+    ("star", 1, (450, 1300), 26, 100, 12), ("box", 1, (611, 1333), 17, 150, 8),
+    ("star", 3, (500, 1200), 9, 120, 4), ("box", 2, (403, 1000), 11, 90, 5),
+    ("star", 2, (700, 1500), 8, 1000, 7)])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
-def test_edge_strip_segments(kind, r, interior, T, seg, dtype):
+def test_edge_strip_segments(kind, r, interior, T, seg, depth, dtype):
     """Edge strips with their own shorter segments give the oracle's result,
-    the same bits as the uniform tiling."""
+    the same bits as the uniform tiling (at depths deep enough for three or
+    more strips, which the edge split needs)."""
     w = wl.random_coeffs(2, kind, r, 83)
     u0 = wl.make_field(interior, r, 83, dtype)
-    info = _check(w, r, u0, T, seg_len=seg)
+    info = _check(w, r, u0, T, seg_len=seg, depth=depth)
     assert info["edge_tiles"] > 0 and info["edge_seg_len"] < info["seg_len"], info
-    got = gpu_sweep(w, r, u0, T, seg_len=seg, flags=8)
-    ref = gpu_sweep(w, r, u0, T, seg_len=seg)
+    got = gpu_sweep(w, r, u0, T, seg_len=seg, depth=depth, flags=8)
+    ref = gpu_sweep(w, r, u0, T, seg_len=seg, depth=depth)
     assert np.array_equal(got, ref)
 
 

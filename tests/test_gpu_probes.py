@@ -42,3 +42,16 @@ def test_neighbor_sync_is_coherent(mode, payload):
           flush=True)
     assert bad == 0
     assert 0 < t < 1e-3
+
+
+def test_calibrate_replaces_the_machine_parameters():
+    try:
+        m = st.stencil_machine_calibrate(st._stream_handle(None))
+        print(json.dumps(m), flush=True)
+        assert m == st.stencil_machine_get()
+        assert 2e12 < m["hbm_bytes_per_s"] < 1.2e13
+        assert 1e13 < m["lds_bytes_per_s"] < 2e14
+        assert 1e-6 < m["grid_sync_s"] < 1e-4 and 1e-7 < m["neighbor_sync_s"] < 1e-4
+        assert m["cus"] == 256
+    finally:
+        st.stencil_machine_set(None)

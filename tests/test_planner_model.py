@@ -1,0 +1,151 @@
+"""The model-driven planner (paper Sections 5-6) on the host: with the MI355X
+machine parameters it picks, for every benchmark configuration, the scheme and
+depth that measure fastest; the choice follows the parameters (a cheaper
+neighbour synchronisation with plentiful bandwidth makes device tiling win in
+3D; the compute-to-bandwidth ratio sets the depth); explicit scheme flags and
+hints override it. No kernel runs."""
+import numpy as np
+import pytest
+
+from paper_2305_07390_amd import stencil as st
+from paper_2305_07390_amd import workloads as wl
+
+NC = st.STENCIL_FLAG_NO_CACHE
+
+
+@pytest.fixture(autouse=True)
+def default_machine():
+    try:
+        st.load_library()
+    except st.StencilLibraryMissing:
+        pytest.skip("libstencil.so not built")
+    st.stencil_machine_set(None)
+    yield
+    st.stencil_machine_set(None)
+
+
+def _plan(spec, interior, dtype, T, seed=2, **kw):
+    p = st.Plan(wl.coeffs_for(spec, seed), spec.r, interior, dtype, T, flags=NC | kw.pop("flags", 0), **kw)
+    info = p.info
+    p.close()
+    return info
+
+
+def test_machine_defaults_are_the_measured_mi355x_values():
+    m = st.stencil_machine_get()
+    assert m["hbm_bytes_per_s"] == pytest.approx(5.1e12)
+    assert m["lds_bytes_per_s"] == pytest.approx(68.7e12)
+    assert m["fp64_flops"] == pytest.approx(256 * 4 * 16 * 2 * 2.15e9)
+    assert m["fp32_flops"] == m["fp64_flops"]  # packed FP32 is not used
+    assert m["grid_sync_s"] == pytest.approx(9.5e-6)
+    assert m["neighbor_sync_s"] == pytest.approx(3.3e-6)
+    assert m["cus"] == 256
+
+
+def test_machine_set_validates_and_resets():
+    with pytest.raises(st.StencilError):
+        st.stencil_machine_set(hbm_bytes_per_s=0.0)
+    st.stencil_machine_set(hbm_bytes_per_s=1e12)
+    assert st.stencil_machine_get()["hbm_bytes_per_s"] == 1e12
+    st.stencil_machine_set(None)
+    assert st.stencil_machine_get()["hbm_bytes_per_s"] == pytest.approx(5.1e12)
+
+
+# (workload, stencil index, expected scheme, expected depth); the depths are
+# the fastest measured on the MI355X for these sizes
+SUITE_2D_PICKS = [(0, 12), (1, 8), (2, 4), (3, 5)]
+SUITE_3D_PICKS = [(0, 4), (1, 2), (2, 2)]
+
+
+@pytest.mark.parametrize("idx,depth", SUITE_2D_PICKS, ids=[s.name for s in wl.SUITE_2D])
+def test_2d_suite_8192_fp64(idx, depth):
+    info = _plan(wl.SUITE_2D[idx], (8192, 8192), np.float64, 1000)
+    assert info["scheme_name"] == "blocked_2d" and info["depth"] == depth
+    assert info["model_cells_per_s"] > 0
+
+
+@pytest.mark.parametrize("idx,depth", SUITE_3D_PICKS, ids=[s.name for s in wl.SUITE_3D])
+def test_3d_suite_512_fp64_prefers_overlapped_tiles(idx, depth):
+    spec = wl.SUITE_3D[idx]
+    info = _plan(spec, (512, 512, 512), np.float64, 200, seed=3)
+    assert info["scheme_name"] == "blocked_3d" and info["depth"] == depth
+    # device tiling applies at 512^3 but the model predicts it slower: one
+    # neighbour synchronisation per z-step against a sub-microsecond step
+    dev = _plan(spec, (512, 512, 512), np.float64, 200, seed=3, flags=st.STENCIL_FLAG_DEVICE_TILING)
+    assert dev["scheme_name"] == "device_3d"
+    assert dev["model_cells_per_s"] < info["model_cells_per_s"]
+
+
+def test_small_jacobi_workload():
+    prob = wl.small_jacobi_problem()
+    p = st.Plan(prob.coeffs, 1, prob.interior, np.float64, prob.T, flags=NC)
+    assert p.info["scheme_name"] == "blocked_2d" and p.info["depth"] == 12 and p.info["passes"] == 2
+    p.close()
+
+
+def test_scheme_choice_follows_the_machine():
+    # With plentiful HBM bandwidth the 3D pass is compute-bound: overlapped
+    # tiles then pay for their redundant margins, device tiling does not, and
+    # with a free neighbour synchronisation device tiling wins. With the
+    # measured synchronisation cost the overlapped tiles win again. (At the
+    # measured bandwidth the 64 x 16 device tile's edge traffic, a third of
+    # its 160 edge cells per 1024 per level, keeps it behind either way: its
+    # short side is below the minimum device tile of paper Section 6.4.)
+    spec = wl.SUITE_3D[0]
+    st.stencil_machine_set(neighbor_sync_s=0.0, hbm_bytes_per_s=100 * 5.1e12)
+    info = _plan(spec, (512, 512, 512), np.float64, 200, seed=3)
+    assert info["scheme_name"] == "device_3d"
+    assert info["redundant_lanes"] == 0
+    st.stencil_machine_set(None)
+    st.stencil_machine_set(hbm_bytes_per_s=100 * 5.1e12)
+    assert _plan(spec, (512, 512, 512), np.float64, 200, seed=3)["scheme_name"] == "blocked_3d"
+    st.stencil_machine_set(None)
+    m = st.stencil_model_eval(B_gm=5.1e12, B_sm=68.7e12, thr_cmp=1.0, cell_bytes=8, a_gm=2, a_sm=4, a_cmp=14,
+                              D_gm=1, D_sm=1, D_cmp=1, D_all=1, t=1, rad=1,
+                              tiling=2, tile=(64, 16))  # device tiling
+    assert 16 < m["min_tile"] < 64
+
+
+def test_scheme_flags_override_the_model():
+    spec = wl.SUITE_3D[0]
+    st.stencil_machine_set(neighbor_sync_s=0.0, hbm_bytes_per_s=100 * 5.1e12)
+    info = _plan(spec, (512, 512, 512), np.float64, 200, seed=3, flags=st.STENCIL_FLAG_OVERLAPPED_TILING)
+    assert info["scheme_name"] == "blocked_3d"
+    st.stencil_machine_set(None)
+    info = _plan(spec, (512, 512, 512), np.float64, 200, seed=3, flags=st.STENCIL_FLAG_DEVICE_TILING)
+    assert info["scheme_name"] == "device_3d"
+    # device tiling does not apply (x not a multiple of 64): overlapped tiles
+    info = _plan(spec, (64, 64, 100), np.float64, 200, seed=3, flags=st.STENCIL_FLAG_DEVICE_TILING)
+    assert info["scheme_name"] == "blocked_3d"
+
+
+def test_desired_depth_follows_the_bandwidth_to_compute_ratio():
+    # paper Section 6.2: the depth that moves the bound off global memory.
+    # With ten times the compute throughput the 25-point box is HBM-bound at
+    # every compiled depth and the deepest wins; with a tenth the redundant
+    # margin's flops dominate and the shallowest wins.
+    spec = wl.SUITE_2D[3]
+    m = st.stencil_machine_get()
+    st.stencil_machine_set(fp64_flops=10 * m["fp64_flops"])
+    deep = _plan(spec, (8192, 8192), np.float64, 1000)["depth"]
+    st.stencil_machine_set(fp64_flops=m["fp64_flops"] / 10)
+    shallow = _plan(spec, (8192, 8192), np.float64, 1000)["depth"]
+    assert deep == st.Plan(wl.coeffs_for(spec, 2), 2, (8192, 8192), np.float64, 1000, depth=64,
+                           flags=NC).info["depth"]
+    assert shallow < deep
+
+
+def test_model_rate_counts_the_redundant_margin():
+    # at equal depth, a wider 2D tile (FP32: 8 columns per lane) loses a
+    # smaller share to its margins than the FP64 tile, so its predicted rate
+    # is more than the 2x of halved bytes would give on HBM alone at depth 1
+    spec = wl.SUITE_2D[0]
+    f64 = _plan(spec, (8192, 8192), np.float64, 1000, depth=4)
+    f32 = _plan(spec, (8192, 8192), np.float32, 1000, depth=4)
+    ratio = f32["model_cells_per_s"] / f64["model_cells_per_s"]
+    assert 1.9 < ratio < 2.2
+
+
+def test_depth_hint_still_wins():
+    info = _plan(wl.SUITE_2D[0], (8192, 8192), np.float64, 1000, depth=3)
+    assert info["depth"] == 3

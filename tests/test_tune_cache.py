@@ -58,7 +58,7 @@ def test_save_load_roundtrip_and_plan_uses_entry(tmp_path):
     out = tmp_path / "saved.json"
     st.stencil_tune_cache_save(str(out))
     saved = json.loads(out.read_text())
-    assert saved["entries"] == [{"key": key, "depth": 5, "seg": 100, "sec_per_step": 1e-4,
+    assert saved["entries"] == [{"key": key, "depth": 5, "seg": 100, "flags": 0, "sec_per_step": 1e-4,
                                  "candidates": 7}]
     st.stencil_tune_cache_clear()
     assert st.stencil_tune_lookup(c, r, (4096, 4096), np.float64) is None
