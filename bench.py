@@ -19,8 +19,10 @@ single-grid suite (512^3, T=200, FP64), the heterogeneous batch of 128 grids
 in one persistent launch per dtype (FP64 and FP32, with the FP32 error against
 the FP64 result and the fraction of its bytes/flops bound) and the serving
 loop under Poisson arrivals (FP32, 200 warm-up + measured requests, p50/p99
-latency, an FP32 error sample, FP64 plain throughput and a small-budget
-stress run).
+latency from each request's scheduled arrival, an FP32 error sample, FP64
+plain throughput, a saturation sweep (400-1600 req/s) that gives the served
+capacity, and a small-budget stress run). The 3D rows carry device tiling's
+best measured rate next to the overlapped tiles the planner picks.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--T 1000]
                        [--no-cpu] [--no-extras] [--serve-seconds S]
@@ -41,15 +43,23 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_TFLOPS = 78.6
-FP32_VALU_TFLOPS = 157.3
+# FP32 as built: packed FP32 is not used, so FP32 FMAs issue at the FP64 rate
+FP32_VALU_TFLOPS = 78.6
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def copy_bandwidth_probe(stencil, nbytes=2 << 30):
+    """Streaming-copy bandwidth of the library's own probe (128-bit loads and
+    stores, best of its kernel variants), read + write bytes / s, GB/s."""
+    return stencil.stencil_probe_copy(nbytes) / 1e9
+
+
 def copy_bandwidth(torch, nbytes=2 << 30, reps=5):
-    """Device-to-device copy bandwidth (read + write bytes / time), GB/s."""
+    """torch's device-to-device copy (read + write bytes / time), GB/s; for
+    comparison with the library's probe."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
@@ -114,21 +124,24 @@ def cpu_baseline(problems, fields, budget_s=15.0):
 KERNEL_SOURCES = ("paper_2305_07390_amd/csrc/tb2d_impl.hpp",
                   "paper_2305_07390_amd/csrc/device_common.hpp")
 TRAFFIC_PROFILE = "profiles/tb2d_traffic_2d_suite_8192.md"
+KERNEL_SOURCES_3D = ("paper_2305_07390_amd/csrc/tb3d_impl.hpp",
+                     "paper_2305_07390_amd/csrc/device_common.hpp")
+TRAFFIC_PROFILE_3D = "profiles/tb3d_traffic_3d_suite_512.md"
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_tag: str):
-    """HBM bytes per launch of `kernel_tag` from the committed PMC summary, or
+def measured_traffic(kernel_tag: str, profile=TRAFFIC_PROFILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of `kernel_tag` from a committed PMC summary, or
     None if the kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    path = os.path.join(ROOT, profile)
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -137,7 +150,7 @@ def measured_traffic(kernel_tag: str):
         if line.startswith("kernel source hash:"):
             src = line.split(":", 1)[1].strip()
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 6 and cells[0] == kernel_tag and src == kernel_source_hash():
+        if len(cells) >= 6 and cells[0] == kernel_tag and src == kernel_source_hash(sources):
             try:
                 return int(float(cells[5]))
             except ValueError:
@@ -227,22 +240,66 @@ def timed(torch, fn):
     return e0.elapsed_time(e1) * 1e-3
 
 
-def bench_3d(torch, np, stencil, workloads, n=512, T=200):
-    """3D single-grid suite, FP64: one timed run per stencil after a warm-up."""
+def bench_3d(torch, np, stencil, workloads, B_gbs, n=512, T=200):
+    """3D single-grid suite, FP64: per stencil, the planner's plan (overlapped
+    tiles) and the best device-tiled plan (every depth, over the same T), one
+    timed run each after a warm-up; each row carries the roofline record of its pass
+    kernel (HBM or VALU bound, the per-launch time from events around the
+    execution divided by its passes) and the model's prediction."""
     rows, total_t, total_u = [], 0.0, 0
+    S = 8
     for prob in workloads.suite_3d_problems(n, T):
         x = torch.from_numpy(prob.field(np.float64)).cuda()
         y = torch.empty_like(x)
         plan = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, prob.T)
         plan.execute(x, y)
         t = timed(torch, lambda: plan.execute(x, y))
-        rows.append({"stencil": prob.spec.name, "scheme": plan.info["scheme_name"],
-                     "depth": plan.info["depth"], "ms": round(t * 1e3, 2),
-                     "gcells_per_s": round(prob.updates / t / 1e9, 1)})
+        info = plan.info
+        t_eff = prob.T / info["passes"]
+        per_launch = t / info["passes"]
+        r_hbm = t_eff * HBM_PEAK_GBS / (2 * S)
+        r_valu = FP64_VALU_TFLOPS * 1e3 / (2 * prob.spec.points)
+        gcells = prob.updates / t / 1e9
+        if r_hbm <= r_valu:
+            roof = {"bound": "hbm", "achieved": round(2 * S * prob.cells / per_launch / 1e9, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        else:
+            roof = {"bound": "alu", "achieved": round(2 * prob.spec.points * prob.cells * info["depth"]
+                                                      / per_launch / 1e12, 2),
+                    "peak": FP64_VALU_TFLOPS, "unit": "TFLOP/s"}
+        roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+        tag = f"tb3d<double,{prob.spec.r},{info['pattern']},{info['depth']}>"
+        roof["traffic"] = measured_traffic(tag, TRAFFIC_PROFILE_3D, KERNEL_SOURCES_3D)
+        roof["kernel_source"] = kernel_source_hash(KERNEL_SOURCES_3D)
+        row = {"stencil": prob.spec.name, "scheme": info["scheme_name"], "depth": info["depth"],
+               "passes": info["passes"], "ms": round(t * 1e3, 2), "gcells_per_s": round(gcells, 1),
+               "avg_launch_us": round(per_launch * 1e6, 2),
+               "fraction": round(gcells / min(t_eff * B_gbs / (2 * S), r_valu), 4),
+               "fraction_spec_hbm": round(gcells / min(r_hbm, r_valu), 4),
+               "model_gcells_per_s": round(info["model_cells_per_s"] / 1e9, 1), "roofline": roof}
+        plan.close()
+        # device tiling: every compiled depth, over the same T steps (the
+        # frame copies and the ring reset of a run amortised as above)
+        best = None
+        dmax = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, prob.T,
+                            flags=stencil.STENCIL_FLAG_DEVICE_TILING).info
+        if dmax["scheme_name"] == "device_3d":
+            for d in range(1, dmax["depth"] + 1):
+                Td = prob.T
+                dp = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, np.float64, Td, depth=d,
+                                  flags=stencil.STENCIL_FLAG_DEVICE_TILING)
+                dp.execute(x, y)
+                td = timed(torch, lambda: dp.execute(x, y))
+                g = prob.cells * Td / td / 1e9
+                if best is None or g > best["gcells_per_s"]:
+                    best = {"depth": d, "gcells_per_s": round(g, 1),
+                            "model_gcells_per_s": round(dp.info["model_cells_per_s"] / 1e9, 1)}
+                dp.close()
+        row["device_tiling_best"] = best
+        rows.append(row)
         total_t += t
         total_u += prob.updates
         log(f"  3d {rows[-1]}")
-        plan.close()
         del x, y
         torch.cuda.empty_cache()
     return {"workload": f"3D single-grid suite {n}^3 FP64, T={T}", "gcells_per_s":
@@ -366,50 +423,24 @@ def bench_paper_benchmarks(torch, np, stencil, workloads):
     return {"workload": "the paper's benchmark stencils at its domain sizes (x fastest), FP64", "per_stencil": rows}
 
 
-def measured_clock_ghz(kernel_tag: str):
-    """Clock under the kernel from the committed SQ/GRBM summary, or None when
-    the kernel source changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "tb2d_sq_counters_2d_suite_8192.md")
-    if not os.path.exists(path):
-        return None
-    src = None
-    for line in open(path).read().splitlines():
-        if line.startswith("kernel source hash:"):
-            src = line.split(":", 1)[1].strip()
-        cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) >= 3 and cells[0] == kernel_tag and src == kernel_source_hash():
-            try:
-                return float(cells[2])
-            except ValueError:
-                return None
-    return None
-
-
 def bench_model_calibration(np, stencil, breakdown, B_gbs):
-    """The attainable-performance model (paper Section 5) per suite stencil,
-    at spec parameters (8 TB/s, 78.6 TF) and calibrated ones (the copy
-    bandwidth measured in this run; the FP64 peak scaled by the clock measured
-    under that kernel), against the measured rate."""
+    """The attainable-performance model (paper Section 5) per suite stencil:
+    the planner's own prediction for the plan it chose (the plan's computed
+    cells, traffic and flops under the library's machine parameters, measured
+    on MI355X), the same model at spec parameters (8 TB/s, 78.6 TF), and the
+    measured rate."""
     rows = []
+    spec = {"hbm_bytes_per_s": HBM_PEAK_GBS * 1e9, "fp64_flops": FP64_VALU_TFLOPS * 1e12,
+            "fp32_flops": FP32_VALU_TFLOPS * 1e12}
+    machine = stencil.stencil_machine_get()
     for row in breakdown:
-        d, r, k = row["depth"], row["radius"], row["points"]
-        V = 4
-        tile = (64.0 * V, row["seg_len"] + 2.0 * d * r)
-        tag = f"tb2d<double,{r},{row['pattern_code']},{d}>"
-        clock = measured_clock_ghz(tag)
-        out = {"stencil": row["stencil"], "measured": row["gcells_per_s"]}
-        for name, B, F in (("spec", 8.0e12, FP64_VALU_TFLOPS * 1e12),
-                           ("calibrated", B_gbs * 1e9, FP64_VALU_TFLOPS * 1e12 * (clock or 2.4) / 2.4)):
-            m = stencil.stencil_model_eval(B_gm=B, thr_cmp=F, cell_bytes=8.0, a_gm=2.0, a_cmp=2.0 * k,
-                                           D_gm=1.0, D_cmp=1.0, D_all=1.0, t=float(d),
-                                           tiling=stencil.MODEL_SM_TILING, tiled_dims=2,
-                                           tile=tile, rad=float(r))
-            out[f"model_{name}"] = round(m["PP"] / 1e9, 1)
-            out[f"measured_over_{name}"] = round(row["gcells_per_s"] / (m["PP"] / 1e9), 3)
-        out["clock_ghz"] = clock
+        out = {"stencil": row["stencil"], "depth": row["depth"], "measured": row["gcells_per_s"],
+               "model_machine": round(row["model_gcells_per_s"], 1)}
+        out["measured_over_model_machine"] = round(row["gcells_per_s"] / max(row["model_gcells_per_s"], 1e-9), 3)
         rows.append(out)
-    return {"note": "PP = P x V with SM-tiling valid fraction; calibrated: B = copy bandwidth of this run, "
-                    "F = 78.6 TF x clock / 2.4 GHz", "per_stencil": rows}
+    return {"note": "model_machine: stencil_plan_info.model_cells_per_s of the executed plan under the "
+                    "library's machine parameters", "machine": machine, "spec_parameters": spec,
+            "copy_probe_GBs": round(B_gbs, 1), "per_stencil": rows}
 
 
 def bench_batch(torch, np, stencil, workloads):
@@ -468,7 +499,11 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
             kept[k] = res
     with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=64) as srv:
         res = serving.serve_open_loop(srv, reqs, arr, on_result=keep)
-    lat = np.array(res["latency_s"][warmup:]) if len(res["latency_s"]) > warmup else np.array(res["latency_s"])
+    # latency from each request's scheduled arrival (the driver's lag to the
+    # submit call included) to the end of the round that completes it
+    alat = res["arrival_latency_s"]
+    lat = np.array(alat[warmup:]) if len(alat) > warmup else np.array(alat)
+    slat_srv = np.array(res["latency_s"][warmup:]) if len(res["latency_s"]) > warmup else np.array(res["latency_s"])
     s = res["stats"]
     # FP32 error against the FP64 path (bit-identical to the oracle in the parity tests)
     err = 0.0
@@ -494,25 +529,47 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
         t64 += timed(torch, lambda: plan.execute(x, y))
         u64 += prob.cells * T
         plan.close()
+    # saturation sweep: offered load past the served capacity; the served
+    # throughput plateaus at the capacity while p99 grows with the queue
+    sweep = []
+    for k, srate in enumerate((400.0, 800.0, 1600.0)):
+        n_s = int(srate * 1.0)
+        wreqs, warr = workloads.serving_requests(n_s, rate_hz=srate, seed=20 + k, dtype=np.float32)
+        with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=64) as srv:
+            wres = serving.serve_open_loop(srv, wreqs, warr)
+        ws = wres["stats"]
+        wl_ = np.array(wres["arrival_latency_s"])
+        woff = sum(p.cells * T for p, _, T in wreqs) / max(float(warr[-1] - warr[0]), 1e-9)
+        sweep.append({"rate": srate, "requests": n_s, "offered_gcells_per_s": round(woff / 1e9, 1),
+                      "served_gcells_per_s": round(ws["cell_updates"] / max(ws["wall_s"], 1e-9) / 1e9, 1),
+                      "p50_ms": round(float(np.percentile(wl_, 50)) * 1e3, 2),
+                      "p99_ms": round(float(np.percentile(wl_, 99)) * 1e3, 2)})
+        log(f"  serving sweep {sweep[-1]}")
     # stress: small budget, twice the rate, so admission binds
     sreqs, sarr = workloads.serving_requests(400, rate_hz=2 * rate, seed=9, dtype=np.float32)
     with serving.Server(hbm_budget_bytes=5 * 10**8, max_slots=64) as srv:
         sres = serving.serve_open_loop(srv, sreqs, sarr)
     ss = sres["stats"]
-    slat = np.array(sres["latency_s"])
+    slat = np.array(sres["arrival_latency_s"])
     out = {"workload": f"Poisson arrivals {rate:g} req/s, {warmup} warm-up + {measured} measured requests, "
                        "grids drawn like the batch (pool of 32), FP32, 200 GB HBM budget",
            "requests": count, "completed": s["completed"], "rejected": len(res["rejected"]),
            "offered_gcells_per_s": round(offered / 1e9, 1),
            "throughput_gcells_per_s": round(s["cell_updates"] / max(s["wall_s"], 1e-9) / 1e9, 1),
            "throughput_req_per_s": round(s["completed"] / max(s["wall_s"], 1e-9), 1),
+           "latency_from": "scheduled arrival",
            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-           "mean_ms": round(float(lat.mean()) * 1e3, 2), "rounds": s["rounds"],
+           "mean_ms": round(float(lat.mean()) * 1e3, 2),
+           "p50_ms_from_submit": round(float(np.percentile(slat_srv, 50)) * 1e3, 2),
+           "p99_ms_from_submit": round(float(np.percentile(slat_srv, 99)) * 1e3, 2),
+           "rounds": s["rounds"],
            "max_active": s["max_active"], "hbm_peak_GB": round(s["hbm_peak"] / 1e9, 2),
            "submit_lag_ms": round(float(res["submit_lag_s"]) * 1e3, 2),
            "f32_max_err_rel_to_max": err, "f32_err_sample": len(kept),
            "fp64_plain_gcells_per_s_first200": round(u64 / max(t64, 1e-9) / 1e9, 1),
+           "saturation_sweep": sweep,
+           "served_fp32_capacity_gcells_per_s": max(r["served_gcells_per_s"] for r in sweep),
            "stress": {"budget_GB": 0.5, "rate": 2 * rate, "requests": 400, "completed": ss["completed"],
                       "rejected": len(sres["rejected"]), "max_active": ss["max_active"],
                       "hbm_peak_GB": round(ss["hbm_peak"] / 1e9, 2),
@@ -576,8 +633,9 @@ def main():
         log(f"  {prob.spec.name}: {plans[-1].info}")
     torch.cuda.synchronize()
 
-    B = copy_bandwidth(torch)
-    log(f"copy bandwidth {B:.0f} GB/s")
+    B = copy_bandwidth_probe(stencil)
+    B_torch = copy_bandwidth(torch)
+    log(f"copy bandwidth {B:.0f} GB/s (library probe), {B_torch:.0f} GB/s (torch copy)")
 
     stream = torch.cuda.current_stream()
 
@@ -639,6 +697,7 @@ def main():
             "avg_launch_us": round(per_launch * 1e6, 2),
             "achieved_GBs": round(bytes_per_launch / per_launch / 1e9, 1),
             "tflops": round(2 * prob.spec.points * prob.updates / t / 1e12, 2),
+            "model_gcells_per_s": round(info["model_cells_per_s"] / 1e9, 1),
         }
         breakdown.append(row)
         if dominant is None or t > dominant[0]:
@@ -683,6 +742,7 @@ def main():
         },
         "roofline": roof,
         "copy_bandwidth_GBs": round(B, 1),
+        "copy_bandwidth_torch_GBs": round(B_torch, 1),
         "per_stencil": breakdown,
     }
     if not args.no_extras:
@@ -706,7 +766,7 @@ def main():
         log("small Jacobi ...")
         result["small_jacobi"] = bench_small_jacobi(torch, np, stencil, workloads)
         log("3D suite ...")
-        result["suite_3d"] = bench_3d(torch, np, stencil, workloads)
+        result["suite_3d"] = bench_3d(torch, np, stencil, workloads, B)
         log("batch ...")
         bench_batch.B = B
         result["batch"] = bench_batch(torch, np, stencil, workloads)

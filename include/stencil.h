@@ -77,7 +77,10 @@ typedef struct {
  *        plan at the interior segment length. By default their tiles, which
  *        also apply the Dirichlet columns and so cost more per row, are cut
  *        into shorter segments that take the wave slots the interior tiles
- *        leave free, so that no pass waits on them (batches set this flag:
+ *        leave free, so that no pass waits on them. The flag also tells the
+ *        planner that the plan's tiles share the device with other jobs, so
+ *        its depth choice does not charge for a round of tiles this grid
+ *        alone would leave part-empty (batches and the server set this flag:
  *        their jobs share the slots);
  *        STENCIL_FLAG_DEVICE_TILING asks a 3D plan for device tiling (paper
  *        Section 4.1, "one tile at a time"): the interior xy plane is split

@@ -227,9 +227,11 @@ namespace stencil_impl {
 // outs[i] on stream s: blocked plans in one persistent launch per dtype, the
 // others with their plain kernels. wsg[i], when not NULL, is the caller's
 // workspace for plan i; the rest of the workspace and control memory is one
-// stream-ordered allocation released on s.
+// stream-ordered allocation (from `pool`, else the device's default pool)
+// released on s.
 stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::vector<const void*>& ins,
-                         const std::vector<void*>& outs, const std::vector<void*>& wsg, hipStream_t s) {
+                         const std::vector<void*>& outs, const std::vector<void*>& wsg, hipStream_t s,
+                         hipMemPool_t pool) {
   const int n = (int)plans.size();
   // groups of blocked jobs by dtype (the fused kernel), FP64 jobs of the
   // auxiliary kernel's variants; everything else runs alone
@@ -341,7 +343,7 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
     }
 
   if (total) {
-    hipError_t e = hipMallocAsync((void**)&dev, total, s);
+    hipError_t e = pool ? hipMallocFromPoolAsync((void**)&dev, total, pool, s) : hipMallocAsync((void**)&dev, total, s);
     if (e != hipSuccess) {
       return fail(STENCIL_ERR_NOMEM, "batch allocation of %zu bytes failed: %s", total,
                   hipGetErrorString(e));
@@ -454,8 +456,57 @@ stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::v
   return st;
 }
 
+// Plans one job of a batch (host only): the caller's depth, else the
+// autotuner's batched depth for its stencil class and size, else the model's,
+// on uniform tiles of segments seg2d / seg3d rows or planes; blocked plans are
+// capped at the fused kernel's depth for their variant, and a job with no
+// batched variant gets the single-grid planner's own plan (it runs alone).
+stencil_status plan_batch_job(const stencil_job& j, int seg2d, int seg3d, stencil_plan_s** out) {
+  *out = nullptr;
+  stencil_tuning hint;
+  std::memset(&hint, 0, sizeof(hint));
+  hint.depth = j.depth;
+  hint.tile[0] = j.shape.ndim == 2 ? seg2d : seg3d;
+  // the jobs share the wave slots; the fused kernel runs overlapped tiles
+  hint.flags = STENCIL_FLAG_UNIFORM_TILES | STENCIL_FLAG_OVERLAPPED_TILING;
+  stencil_plan_t pl = nullptr;
+  stencil_status st = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+  int tuned_depth = 0, tuned_seg = 0;
+  if (st == STENCIL_OK && j.depth <= 0 && tune_lookup_plan(pl, true, &tuned_depth, &tuned_seg) &&
+      tuned_depth != pl->depth) {
+    // the autotuner's depth for batched tiles of this stencil class and size
+    stencil_plan_destroy(pl);
+    pl = nullptr;
+    hint.depth = tuned_depth;
+    st = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+  }
+  if (st == STENCIL_OK && (pl->scheme == STENCIL_SCHEME_BLOCKED_2D || pl->scheme == STENCIL_SCHEME_BLOCKED_3D)) {
+    // the fused batch kernel's own depth limit for this variant
+    const int dt = pl->dtype == STENCIL_F64 ? kF64 : kF32;
+    int cap = batch_max_depth(dt, pl->ndim, pl->r, pl->pattern);
+    if (cap == 0) cap = batch_aux_depth(dt, pl->ndim, pl->r, pl->pattern);
+    if (cap >= 1 && pl->depth > cap) {
+      stencil_plan_destroy(pl);
+      pl = nullptr;
+      hint.depth = cap;
+      st = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+    } else if (cap == 0) {
+      // no batched variant: the job runs alone after the persistent launch,
+      // with the single-grid planner's own segments (enough tiles to fill
+      // the device on its own, unlike the batch's long segments)
+      stencil_plan_destroy(pl);
+      pl = nullptr;
+      hint.tile[0] = 0;
+      hint.flags = 0;
+      st = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
+    }
+  }
+  if (st == STENCIL_OK) *out = pl;
+  return st;
+}
+
 stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stream,
-                                  stencil_status* per_job_status, int seg2d, int seg3d) {
+                                  stencil_status* per_job_status, int seg2d, int seg3d, hipMemPool_t pool) {
   if (!jobs || n <= 0) return fail(STENCIL_ERR_INVALID, "no jobs");
   hipStream_t s = (hipStream_t)stream;
   std::vector<stencil_status> status(n, STENCIL_OK);
@@ -468,44 +519,8 @@ stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stre
       status[i] = fail(STENCIL_ERR_INVALID, "job %d: in/out is NULL", i);
       continue;
     }
-    stencil_tuning hint;
-    std::memset(&hint, 0, sizeof(hint));
-    hint.depth = j.depth;
-    hint.tile[0] = j.shape.ndim == 2 ? seg2d : seg3d;
-    hint.flags = STENCIL_FLAG_UNIFORM_TILES;  // the jobs share the wave slots
     stencil_plan_t pl = nullptr;
-    status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
-    int tuned_depth = 0, tuned_seg = 0;
-    if (status[i] == STENCIL_OK && j.depth <= 0 &&
-        tune_lookup_plan(pl, true, &tuned_depth, &tuned_seg) && tuned_depth != pl->depth) {
-      // the autotuner's depth for batched tiles of this stencil class and size
-      stencil_plan_destroy(pl);
-      pl = nullptr;
-      hint.depth = tuned_depth;
-      status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
-    }
-    if (status[i] == STENCIL_OK &&
-        (pl->scheme == STENCIL_SCHEME_BLOCKED_2D || pl->scheme == STENCIL_SCHEME_BLOCKED_3D)) {
-      // the fused batch kernel's own depth limit for this variant
-      const int dt = pl->dtype == STENCIL_F64 ? kF64 : kF32;
-      int cap = batch_max_depth(dt, pl->ndim, pl->r, pl->pattern);
-      if (cap == 0) cap = batch_aux_depth(dt, pl->ndim, pl->r, pl->pattern);
-      if (cap >= 1 && pl->depth > cap) {
-        stencil_plan_destroy(pl);
-        pl = nullptr;
-        hint.depth = cap;
-        status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
-      } else if (cap == 0) {
-        // no batched variant: the job runs alone after the persistent launch,
-        // with the single-grid planner's own segments (enough tiles to fill
-        // the device on its own, unlike the batch's long segments)
-        stencil_plan_destroy(pl);
-        pl = nullptr;
-        hint.tile[0] = 0;
-        hint.flags = 0;
-        status[i] = stencil_plan(&pl, j.coeffs, j.radius, &j.shape, j.dtype, j.T, &hint);
-      }
-    }
+    status[i] = plan_batch_job(j, seg2d, seg3d, &pl);
     if (status[i] == STENCIL_OK) {
       const size_t bytes = (size_t)pl->padded_elems * pl->elem;
       const char* a = (const char*)j.in;
@@ -549,7 +564,7 @@ stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stre
     ins[i] = jobs[i].in;
     outs[i] = jobs[i].out;
   }
-  stencil_status st = batch_run(plans, ins, outs, wsg, s);
+  stencil_status st = batch_run(plans, ins, outs, wsg, s, pool);
   for (auto* p : plans) stencil_plan_destroy(p);
   return st;
 }

@@ -523,6 +523,7 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
     // among the candidates within 3% of the best prediction the deepest (the
     // fewest passes) wins.
     std::vector<std::pair<double, stencil_plan_s>> cands;
+    p->shared = (hflags & STENCIL_FLAG_UNIFORM_TILES) != 0;
     auto consider = [&](const stencil_plan_s& c) { cands.emplace_back(plan_model_rate(&c), c); };
     if (!force_naive && p->ndim == 2 && radius >= 1 && p->points > 0) {
       const int V = tb2d_cols_per_lane(dtype, radius, p->pattern);

@@ -84,7 +84,7 @@ stencil_machine machine() {
 //   blocked 2D: every tile computes and reads its 64V-column strip over its
 //     segment plus 2 d r warm-up rows; writes are the valid cells; no LDS in
 //     the level loop (registers and DPP); tiles run in rounds of one per
-//     SIMD;
+//     SIMD (a batched plan's rounds are filled by the other jobs);
 //   blocked 3D: every tile computes and reads 64 x 16 BY cells over its
 //     segment plus 2 d r warm-up planes; per level the lanes exchange their
 //     top and bottom rows through LDS; tiles run in rounds of one per CU;
@@ -111,9 +111,10 @@ double plan_model_rate(const stencil_plan_s* p) {
       computed = cols * (double)p->strips * p->segs * rows(p->seg_len);
     t_pass = pass_time(m, f64, computed + N, 0.0, computed * d, p->points);
     // one tile per SIMD at a time: tiles run in rounds over the wave slots,
-    // and a round with fewer tiles than slots leaves the rest idle
+    // and a round with fewer tiles than slots leaves the rest idle (unless
+    // other jobs' tiles fill it)
     const double slots = 4.0 * m.cus;
-    t_pass *= std::ceil(p->tiles / slots) * slots / (double)p->tiles;
+    if (!p->shared) t_pass *= std::ceil(p->tiles / slots) * slots / (double)p->tiles;
   } else if (p->scheme == STENCIL_SCHEME_BLOCKED_3D) {
     const double BY = tb3d_cells_y(f64 ? kF64 : kF32, p->r, p->pattern);
     const double tile_cells = 64.0 * 16.0 * BY;
@@ -122,9 +123,10 @@ double plan_model_rate(const stencil_plan_s* p) {
     // per level and cell: its rows shared with the lanes above and below
     const double lds_cells = computed * d * (1.0 + 2.0 * std::min(r, BY) / BY);
     t_pass = pass_time(m, f64, computed + N, lds_cells, computed * d, p->points);
-    // one tile per CU at a time: the last round runs part-empty
+    // one tile per CU at a time: the last round runs part-empty (unless
+    // other jobs' tiles fill it)
     const double rounds = std::ceil((double)p->tiles / m.cus);
-    t_pass *= rounds * m.cus / (double)p->tiles;
+    if (!p->shared) t_pass *= rounds * m.cus / (double)p->tiles;
   } else if (p->scheme == STENCIL_SCHEME_DEVICE_3D) {
     const double zsteps = (double)tb3d_dev_iterations(p->r, p->depth, p->ext[0]);
     const double edge_cells = (double)p->tiles * 2.0 * r * (64.0 + tb3d_dev_tile_y());

@@ -30,9 +30,16 @@ namespace stencil_impl {
 // overlapped tiling).
 bool tune_lookup_plan(const stencil_plan_s* pl, bool batched, int* depth, int* seg, int* flags = nullptr);
 // Prepared plans through the persistent batch kernel (batch_host.cpp).
-// stencil_batch_submit with explicit batch tile lengths (2D rows, 3D planes).
+// stencil_batch_submit with explicit batch tile lengths (2D rows, 3D planes);
+// the launch's device memory comes from `pool` (NULL: the device's default
+// stream-ordered pool).
 stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stream,
-                                  stencil_status* per_job_status, int seg2d, int seg3d);
+                                  stencil_status* per_job_status, int seg2d, int seg3d,
+                                  hipMemPool_t pool = nullptr);
+// One batch job's plan: its depth, else the autotuner's batched depth, else
+// the model's, on uniform tiles of seg2d rows / seg3d planes, capped at the
+// fused kernel's depth (a job with no batched variant: a single-grid plan).
+stencil_status plan_batch_job(const stencil_job& j, int seg2d, int seg3d, stencil_plan_s** out);
 int serve_seg_2d();
 int serve_seg_3d();
 // The model's machine parameters and its predicted rate of a plan
@@ -44,7 +51,8 @@ double plan_model_rate(const stencil_plan_s* p);
 int64_t watchdog_ticks();
 unsigned int* stream_report_word(hipStream_t s);
 stencil_status batch_run(const std::vector<stencil_plan_s*>& plans, const std::vector<const void*>& ins,
-                         const std::vector<void*>& outs, const std::vector<void*>& wsg, hipStream_t s);
+                         const std::vector<void*>& outs, const std::vector<void*>& wsg, hipStream_t s,
+                         hipMemPool_t pool = nullptr);
 }  // namespace stencil_impl
 
 struct stencil_plan_s {
@@ -78,6 +86,9 @@ struct stencil_plan_s {
   std::vector<int64_t> tap_off;
   std::vector<double> tap_w;
   bool persistent = false;  // all passes in one persistent launch
+  // planned for a batch: its tiles share the device with other jobs', so a
+  // round of tiles left part-empty by this grid is filled by theirs
+  bool shared = false;
   // device-tiled 3D plan: byte offsets of the halo ring and of the control
   // words (progress counters, then the error word) in the workspace
   size_t dev_ring_off = 0, dev_ring_bytes = 0, dev_ctl_off = 0;

@@ -95,6 +95,12 @@ struct Request {
 struct stencil_server_s {
   stencil_server_config cfg;
   hipStream_t compute = nullptr, copy = nullptr, collect = nullptr;
+  // the server's own stream-ordered pool: request grids and round workspaces
+  // come from it, and it keeps freed memory up to the budget instead of
+  // returning it to the driver at every synchronisation (the default pool's
+  // behaviour), so admissions reuse memory rather than map new pages while
+  // the scheduler holds the lock
+  hipMemPool_t pool = nullptr;
   hipEvent_t round_end = nullptr, inputs_ready = nullptr, copy_mark = nullptr;
   std::mutex mu;
   std::condition_variable cv_work;  // new submissions or stop
@@ -152,7 +158,7 @@ void admit_locked(stencil_server_s* srv) {
     if (srv->st.hbm_in_use + r->need > srv->cfg.hbm_budget_bytes) break;
     srv->queue.pop_front();
     const size_t two = 2 * align256(r->bytes);
-    hipError_t e = hipMallocAsync((void**)&r->dev, two, srv->copy);
+    hipError_t e = hipMallocFromPoolAsync((void**)&r->dev, two, srv->pool, srv->copy);
     if (e == hipSuccess)
       e = hipMemcpyAsync(r->dev, r->host_in, r->bytes, hipMemcpyHostToDevice, srv->copy);
     if (e != hipSuccess) {
@@ -233,7 +239,7 @@ void scheduler(stencil_server_s* srv) {
     const Clock::time_point t0 = Clock::now();
     if (st == STENCIL_OK)
       st = batch_submit_tiles(jobs.data(), (int32_t)jobs.size(), srv->compute, js.data(), serve_seg_2d(),
-                              serve_seg_3d());
+                              serve_seg_3d(), srv->pool);
     if (st == STENCIL_OK && hipEventRecord(srv->round_end, srv->compute) != hipSuccess)
       st = hip_fail(hipErrorUnknown, "server round event");
     // while the round runs, admit arrivals so their inputs are on the device
@@ -380,6 +386,17 @@ stencil_status stencil_server_create(const stencil_server_config* config, stenci
   if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->round_end, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->inputs_ready, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->copy_mark, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    hipMemPoolProps props;
+    std::memset(&props, 0, sizeof(props));
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = config->device;
+    e = hipMemPoolCreate(&srv->pool, &props);
+    uint64_t keep = config->hbm_budget_bytes;
+    if (e == hipSuccess) e = hipMemPoolSetAttribute(srv->pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   (void)hipSetDevice(prev);
   if (e != hipSuccess) {
     stencil_server_destroy(srv.release());
@@ -396,8 +413,10 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
   if (!srv || !job || !host_in || !ticket) return fail(STENCIL_ERR_INVALID, "NULL argument");
   // latency counts from the call, so planning and host staging are inside it
   const Clock::time_point t_call = Clock::now();
+  // planned as a round's batch plans it: the depth found here is the one
+  // every round then runs the request at
   stencil_plan_t pl = nullptr;
-  stencil_status st = stencil_plan(&pl, job->coeffs, job->radius, &job->shape, job->dtype, job->T, nullptr);
+  stencil_status st = plan_batch_job(*job, serve_seg_2d(), serve_seg_3d(), &pl);
   if (st != STENCIL_OK) {
     std::lock_guard<std::mutex> lock(srv->mu);
     srv->st.rejected++;
@@ -413,13 +432,7 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
   r->need = 2 * align256(r->bytes) + align256(r->bytes);
   r->remaining = job->T;
   r->updates = (double)pl->cells * (double)job->T;
-  const int dt = pl->dtype == STENCIL_F64 ? kF64 : kF32;
-  int depth = pl->depth;
-  if (pl->scheme == STENCIL_SCHEME_BLOCKED_2D || pl->scheme == STENCIL_SCHEME_BLOCKED_3D)
-    depth = std::max(1, std::min(depth, batch_max_depth(dt, pl->ndim, pl->r, pl->pattern)));
-  else
-    depth = 1;
-  r->depth = std::max(1, depth);
+  r->depth = pl->scheme == STENCIL_SCHEME_NAIVE ? 1 : std::max(1, pl->depth);
   r->cells = std::max<int64_t>(1, pl->cells);
   r->coeffs = pl->coeffs;
   stencil_plan_destroy(pl);
@@ -433,7 +446,7 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
   r->job.coeffs = r->coeffs.data();
   r->job.in = nullptr;
   r->job.out = nullptr;
-  r->job.depth = 0;
+  r->job.depth = r->depth;
   r->host_in = srv->pinned.get(r->bytes, &r->host_cls);
   if (!r->host_in) return fail(STENCIL_ERR_NOMEM, "pinned staging of %zu bytes failed", r->bytes);
   std::memcpy(r->host_in, host_in, r->bytes);
@@ -513,6 +526,8 @@ stencil_status stencil_server_destroy(stencil_server_t srv) {
   if (srv->compute) (void)hipStreamDestroy(srv->compute);
   if (srv->copy) (void)hipStreamDestroy(srv->copy);
   if (srv->collect) (void)hipStreamDestroy(srv->collect);
+  // every allocation from the pool has been freed and its stream drained
+  if (srv->pool) (void)hipMemPoolDestroy(srv->pool);
   (void)hipSetDevice(prev);
   delete srv;
   return STENCIL_OK;

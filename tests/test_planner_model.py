@@ -149,3 +149,26 @@ def test_model_rate_counts_the_redundant_margin():
 def test_depth_hint_still_wins():
     info = _plan(wl.SUITE_2D[0], (8192, 8192), np.float64, 1000, depth=3)
     assert info["depth"] == 3
+
+
+@pytest.mark.parametrize("idx", range(4), ids=[s.name for s in wl.SUITE_2D])
+def test_shared_tiles_plan_like_a_full_device(idx):
+    # A 1024^2 grid alone leaves most wave slots idle in its last round of
+    # tiles, which favours shallow depths; planned for a batch (uniform tiles,
+    # the slots shared with other jobs) the same grid takes the depth a grid
+    # that fills the device would take.
+    spec = wl.SUITE_2D[idx]
+    alone = _plan(spec, (1024, 1024), np.float32, 400)
+    shared = _plan(spec, (1024, 1024), np.float32, 400, seg_len=256, flags=st.STENCIL_FLAG_UNIFORM_TILES)
+    full = _plan(spec, (8192, 8192), np.float32, 400)
+    assert alone["depth"] < shared["depth"]
+    assert abs(shared["depth"] - full["depth"]) <= 1
+
+
+def test_shared_3d_tiles_plan_like_a_full_device():
+    spec = wl.SUITE_3D[0]
+    fl = st.STENCIL_FLAG_UNIFORM_TILES | st.STENCIL_FLAG_OVERLAPPED_TILING
+    alone = _plan(spec, (64, 128, 128), np.float32, 400)
+    shared = _plan(spec, (64, 128, 128), np.float32, 400, seg_len=64, flags=fl)
+    full = _plan(spec, (512, 512, 512), np.float32, 400)
+    assert alone["depth"] < shared["depth"] == full["depth"]
