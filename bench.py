@@ -125,8 +125,14 @@ KERNEL_SOURCES = ("paper_2305_07390_amd/csrc/tb2d_impl.hpp",
                   "paper_2305_07390_amd/csrc/device_common.hpp")
 TRAFFIC_PROFILE = "profiles/tb2d_traffic_2d_suite_8192.md"
 KERNEL_SOURCES_3D = ("paper_2305_07390_amd/csrc/tb3d_impl.hpp",
+                     "paper_2305_07390_amd/csrc/tb3d_dev_impl.hpp",
                      "paper_2305_07390_amd/csrc/device_common.hpp")
 TRAFFIC_PROFILE_3D = "profiles/tb3d_traffic_3d_suite_512.md"
+KERNEL_SOURCES_BATCH = ("paper_2305_07390_amd/csrc/batch_impl.hpp",
+                        "paper_2305_07390_amd/csrc/tb2d_impl.hpp",
+                        "paper_2305_07390_amd/csrc/tb3d_impl.hpp",
+                        "paper_2305_07390_amd/csrc/device_common.hpp")
+TRAFFIC_PROFILE_BATCH = "profiles/batch_traffic_128_grids.md"
 
 
 def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
@@ -147,8 +153,8 @@ def measured_traffic(kernel_tag: str, profile=TRAFFIC_PROFILE, sources=KERNEL_SO
     text = open(path).read()
     src = None
     for line in text.splitlines():
-        if line.startswith("kernel source hash:"):
-            src = line.split(":", 1)[1].strip()
+        if line.startswith("kernel source hash"):
+            src = line.rsplit(":", 1)[1].strip()
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
         if len(cells) >= 6 and cells[0] == kernel_tag and src == kernel_source_hash(sources):
             try:
@@ -158,14 +164,29 @@ def measured_traffic(kernel_tag: str, profile=TRAFFIC_PROFILE, sources=KERNEL_SO
     return None
 
 
+def calibration_copy(torch):
+    """A 512 MiB device copy: the known-size kernel that scales the HBM
+    counters (FETCH_SIZE, WRITE_SIZE) of the other dispatches."""
+    a = torch.empty(512 << 18, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"probe: copy of {a.numel() * 4} bytes")
+    del a, b
+
+
 def probe3d():
-    """Short program for 3D counter passes: two passes of each 3D suite stencil
-    (512^3, FP64 and FP32) at its planned depth."""
+    """Short program for 3D counter passes: the calibration copy, two passes of
+    each 3D suite stencil (512^3, FP64 and FP32) at its planned depth, and one
+    device-tiled run of each at its deepest compiled depth over 2 x depth
+    steps."""
     import numpy as np
     import torch
 
     from paper_2305_07390_amd import stencil, workloads
     torch.cuda.set_device(0)
+    calibration_copy(torch)
     for prob in workloads.suite_3d_problems(512, 200):
         for dt in (np.float64, np.float32):
             x = torch.from_numpy(prob.field(dt)).cuda()
@@ -178,17 +199,30 @@ def probe3d():
             torch.cuda.synchronize()
             log(f"probe3d: {prob.spec.name} {np.dtype(dt).name} depth {d} passes {plan.info['passes']}")
             plan.close()
+            dev = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, dt, 64, depth=64,
+                               flags=stencil.STENCIL_FLAG_DEVICE_TILING)
+            dd = dev.info["depth"]
+            dev.close()
+            dev = stencil.Plan(prob.coeffs, prob.spec.r, prob.interior, dt, 2 * dd, depth=dd,
+                               flags=stencil.STENCIL_FLAG_DEVICE_TILING)
+            if dev.info["scheme_name"] == "device_3d":
+                dev.execute(x, y)
+                torch.cuda.synchronize()
+                log(f"probe3d: {prob.spec.name} {np.dtype(dt).name} device tiling depth {dd}")
+            dev.close()
             del x, y
             torch.cuda.empty_cache()
 
 
 def probe_batch():
-    """One run of the 128-grid batch per dtype (for kernel traces)."""
+    """The calibration copy, then one run of the 128-grid batch per dtype (for
+    kernel traces and counter passes)."""
     import numpy as np
     import torch
 
     from paper_2305_07390_amd import stencil, workloads
     torch.cuda.set_device(0)
+    calibration_copy(torch)
     probs = workloads.batch_problems()
     for dt in (np.float64, np.float32):
         xs = [torch.from_numpy(p.field(np.float64).astype(dt)).cuda() for p in probs]
@@ -208,12 +242,7 @@ def probe():
 
     from paper_2305_07390_amd import stencil, workloads
     torch.cuda.set_device(0)
-    a = torch.empty(512 << 18, dtype=torch.float32, device="cuda")
-    a.fill_(1.0)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    log(f"probe: copy of {a.numel() * 4} bytes")
+    calibration_copy(torch)
     for prob in workloads.suite_2d_problems(8192, 1000):
         x = torch.from_numpy(prob.field()).cuda()
         y = torch.empty_like(x)
@@ -390,15 +419,15 @@ def bench_small_jacobi(torch, np, stencil, workloads, reps=20):
 
 
 def batch_bound_seconds(np, stencil, probs, dtype, B):
-    """max(sum of algorithmic bytes / B, sum of flops / F) for a batch."""
+    """max(sum of algorithmic bytes / B, sum of flops / F) for a batch: each
+    pass of the plan the batch runs a job with reads and writes its grid once."""
     S = 8 if dtype == np.float64 else 4
     F = (FP64_VALU_TFLOPS if dtype == np.float64 else FP32_VALU_TFLOPS) * 1e12
     nbytes = 0.0
     nflops = 0.0
     for p in probs:
-        plan = stencil.Plan(p.coeffs, p.spec.r, p.interior, dtype, p.T)
-        nbytes += 2.0 * S * p.cells * plan.info["passes"]
-        plan.close()
+        info = stencil.stencil_batch_describe(p.coeffs, p.spec.r, p.interior, dtype, p.T)
+        nbytes += 2.0 * S * p.cells * info["passes"]
         nflops += 2.0 * p.spec.points * p.updates
     return max(nbytes / (B * 1e9), nflops / F), nbytes, nflops
 
@@ -461,6 +490,15 @@ def bench_batch(torch, np, stencil, workloads):
         out[name] = {"s": round(t, 4), "gcells_per_s": round(upd / t / 1e9, 1),
                      "bound_s": round(bound, 4), "fraction_of_bound": round(bound / t, 4),
                      "algorithmic_GB": round(nbytes / 1e9, 2), "tflop": round(nflops / 1e12, 2)}
+        # HBM bytes per launch of each batch kernel from the committed counter
+        # summary (None once the kernel sources changed)
+        tname = "double" if dt == np.float64 else "float"
+        kernels = (f"batch<{tname},0>", f"batch<{tname},1>") if dt == np.float64 else (f"batch<{tname},0>",)
+        traffic = {k: measured_traffic(k, TRAFFIC_PROFILE_BATCH, KERNEL_SOURCES_BATCH) for k in kernels}
+        out[name]["traffic_bytes"] = traffic
+        if all(v is not None for v in traffic.values()):
+            out[name]["traffic_over_algorithmic"] = round(sum(traffic.values()) / nbytes, 3)
+        out[name]["kernel_source"] = kernel_source_hash(KERNEL_SOURCES_BATCH)
         log(f"  batch {name}: {out[name]}")
         ys_by[name] = ys
         del xs

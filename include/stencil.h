@@ -219,6 +219,14 @@ typedef struct {
 stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* stream,
                                     stencil_status* per_job_status);
 
+/* Host only: describes the plan stencil_batch_submit runs `job` with (scheme,
+ * depth, passes, tiles; its in/out pointers are not read). Batched plans use
+ * uniform tiles of the batch's segment lengths, are capped at the fused
+ * kernel's depth for their variant, and take their depth from the model as
+ * if the device were full (the other jobs fill it). STENCIL_ERR_INVALID for
+ * NULL arguments; planning errors as stencil_plan. */
+stencil_status stencil_batch_describe(const stencil_job* job, stencil_plan_info* info);
+
 /* Wait for `stream` and report device-side failures of the library's kernels
  * enqueued on that stream since the last call on it: STENCIL_ERR_TIMEOUT if a
  * bounded wait expired (the affected results are undefined), STENCIL_ERR_DEVICE

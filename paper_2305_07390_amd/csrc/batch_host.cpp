@@ -586,6 +586,16 @@ stencil_status stencil_batch_submit(const stencil_job* jobs, int32_t n, void* st
   return batch_submit_tiles(jobs, n, stream, per_job_status, kBatchSeg2D, kBatchSeg3D);
 }
 
+stencil_status stencil_batch_describe(const stencil_job* job, stencil_plan_info* info) {
+  if (!job || !info) return fail(STENCIL_ERR_INVALID, "NULL argument");
+  stencil_plan_s* pl = nullptr;
+  stencil_status st = plan_batch_job(*job, kBatchSeg2D, kBatchSeg3D, &pl);
+  if (st != STENCIL_OK) return st;
+  st = stencil_plan_describe(pl, info);
+  stencil_plan_destroy(pl);
+  return st;
+}
+
 stencil_status stencil_probe_grid_sync(int32_t rounds, void* stream, double* seconds_per_sync) {
   if (!seconds_per_sync || rounds < 1 || rounds > 1000000)
     return fail(STENCIL_ERR_INVALID, "rounds in [1, 1e6] and a result pointer");

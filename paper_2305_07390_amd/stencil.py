@@ -162,6 +162,7 @@ _SIGNATURES = {
                                             ctypes.c_int, ctypes.c_int64, _P, _P, _P]),
     "stencil_batch_submit": (ctypes.c_int, [ctypes.POINTER(stencil_job), ctypes.c_int32, _P,
                                              ctypes.POINTER(ctypes.c_int)]),
+    "stencil_batch_describe": (ctypes.c_int, [ctypes.POINTER(stencil_job), ctypes.POINTER(stencil_plan_info)]),
     "stencil_sync": (ctypes.c_int, [_P]),
     "stencil_probe_grid_sync": (ctypes.c_int, [ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
     "stencil_probe_copy": (ctypes.c_int, [ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_double)]),
@@ -359,6 +360,21 @@ def stencil_batch_submit(specs, stream: int = 0):
     st = (ctypes.c_int * n)()
     _check(lib.stencil_batch_submit(arr, n, stream or None, st))
     return list(st)
+
+
+def stencil_batch_describe(coeffs, radius: int, interior, dtype, T: int, depth: int = 0) -> dict:
+    """The plan stencil_batch_submit would run this job with (host only)."""
+    lib = load_library()
+    job = stencil_job()
+    c, job.coeffs = _coeff_ptr(coeffs)
+    job.radius = int(radius)
+    job.shape = _shape(interior)
+    job.dtype = _dtype_code(dtype)
+    job.T = int(T)
+    job.depth = int(depth)
+    info = stencil_plan_info()
+    _check(lib.stencil_batch_describe(ctypes.byref(job), ctypes.byref(info)))
+    return info.as_dict()
 
 
 def stencil_probe_grid_sync(rounds: int = 1000, stream: int = 0) -> float:

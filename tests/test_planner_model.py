@@ -172,3 +172,21 @@ def test_shared_3d_tiles_plan_like_a_full_device():
     shared = _plan(spec, (64, 128, 128), np.float32, 400, seg_len=64, flags=fl)
     full = _plan(spec, (512, 512, 512), np.float32, 400)
     assert alone["depth"] < shared["depth"] == full["depth"]
+
+
+def test_batch_describe_reports_the_batched_plan():
+    # the 128-grid batch: every job planned as the batch runs it, never
+    # shallower than the same grid planned alone, and never device-tiled
+    probs = wl.batch_problems()
+    deeper = 0
+    for p in probs:
+        for dt in (np.float64, np.float32):
+            info = st.stencil_batch_describe(p.coeffs, p.spec.r, p.interior, dt, p.T)
+            alone = _plan(p.spec, p.interior, dt, p.T, seed=0)
+            assert info["scheme_name"] in ("blocked_2d", "blocked_3d")
+            assert info["passes"] == -(-p.T // info["depth"])
+            assert info["depth"] >= alone["depth"] or p.T < alone["depth"]
+            deeper += info["depth"] > alone["depth"]
+    assert deeper > len(probs) // 2
+    with pytest.raises(st.StencilError):
+        st.stencil_batch_describe(probs[0].coeffs, probs[0].spec.r, probs[0].interior, np.float64, -1)
