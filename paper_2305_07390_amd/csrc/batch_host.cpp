@@ -19,6 +19,7 @@
 
 #include "launch.hpp"
 #include "plan.hpp"
+#include "worklist.hpp"
 
 using namespace stencil_impl;
 
@@ -155,36 +156,17 @@ struct Group {
 constexpr int kAuxGroup = 2;  // groups: kF32, kF64, then the FP64 auxiliary group
 
 // Work-list items of one pass: a 3D tile, or up to four 2D wave tiles.
-int64_t items_per_pass(const stencil_plan_s* p) {
-  return p->ndim == 2 ? (p->tiles + 3) / 4 : p->tiles;
-}
+int64_t items_per_pass(const stencil_plan_s* p) { return worklist::items_per_pass(p->ndim, p->tiles); }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Work list of a group: chunks (job, pass) in order of progress after the
-// chunk; ties by job index. Every pass of a job follows its previous pass.
+// Work list of a group (worklist::build): every pass of a job follows its
+// previous pass.
 void build_worklist(const std::vector<stencil_plan_s*>& plans, const std::vector<int>& members,
                     std::vector<int32_t>& cj, std::vector<int32_t>& cp, std::vector<int64_t>& cf) {
-  struct C { double key; int job, pass; };
-  std::vector<C> chunks;
-  for (int local = 0; local < (int)members.size(); ++local) {
-    const stencil_plan_s* p = plans[members[local]];
-    const int np = (int)p->pass_depth.size();
-    for (int k = 0; k < np; ++k) chunks.push_back({(double)(k + 1) / np, local, k});
-  }
-  std::stable_sort(chunks.begin(), chunks.end(), [](const C& a, const C& b) {
-    if (a.key != b.key) return a.key < b.key;
-    if (a.job != b.job) return a.job < b.job;
-    return a.pass < b.pass;
-  });
-  cj.clear();
-  cp.clear();
-  cf.assign(1, 0);
-  for (const C& c : chunks) {
-    cj.push_back(c.job);
-    cp.push_back(c.pass);
-    cf.push_back(cf.back() + items_per_pass(plans[members[c.job]]));
-  }
+  std::vector<worklist::JobShape> shapes;
+  for (int i : members) shapes.push_back({(int32_t)plans[i]->pass_depth.size(), items_per_pass(plans[i])});
+  worklist::build(shapes, cj, cp, cf);
 }
 
 template <typename Real>
@@ -654,11 +636,11 @@ stencil_status stencil_sync(void* stream) {
       if (e != hipSuccess) return hip_fail(e, "error word read");
     }
   }
-  if (h) {
+  if (worklist::status_of_report(h) != STENCIL_OK) {
     e = hipMemsetAsync(err, 0, sizeof(unsigned int), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "error word reset");
-    return fail(STENCIL_ERR_TIMEOUT, "a bounded device wait expired; affected results are undefined");
+    return fail(worklist::status_of_report(h), "a bounded device wait expired; affected results are undefined");
   }
   return STENCIL_OK;
 }

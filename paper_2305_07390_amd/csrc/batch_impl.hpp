@@ -11,6 +11,7 @@
 #pragma once
 #include "tb2d_impl.hpp"
 #include "tb3d_impl.hpp"
+#include "worklist.hpp"
 
 // One translation unit per dtype instantiates the kernel; see batch_f*.hip.
 
@@ -38,38 +39,23 @@ __device__ __forceinline__ T* uni_ptr(T* p) {
   return (T*)(uintptr_t)uni((int64_t)(uintptr_t)p);
 }
 
-// Chunk holding item `it`: the largest c with chunk_first[c] <= it.
-__device__ __forceinline__ int find_chunk(const BatchQueue& q, int64_t it) {
-  int lo = 0, hi = q.nchunks;  // chunk_first[lo] <= it < chunk_first[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (q.chunk_first[mid] <= it) lo = mid;
-    else hi = mid;
+// Memory operations and clock of the work-list waits on the device. Every
+// value that steers a wait is made wave-uniform, so the compiler keeps the
+// persistent item loop around it uniform too (a loop it believed divergent
+// was restructured into a lane-masked one).
+struct DeviceWait {
+  __device__ static unsigned load_acquire(const unsigned* p) {
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
   }
-  return lo;
-}
-
-// Wait until *ctr >= need. Returns false if the watchdog expired here or an
-// earlier wait of the launch already failed. Every value that steers the loop
-// is made wave-uniform, so the compiler keeps the persistent item loop around
-// it uniform too (a loop it believed divergent was restructured into a
-// lane-masked one).
-__device__ __forceinline__ bool wait_count(const BatchQueue& q, const unsigned* ctr, unsigned need) {
-  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-  while (true) {
-    const unsigned v = __builtin_amdgcn_readfirstlane(
-        __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-    if (v >= need) return true;
-    const unsigned e = __builtin_amdgcn_readfirstlane(
-        __hip_atomic_load(q.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if (e != 0u) return false;
-    if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > q.timeout_ticks) {
-      __hip_atomic_store(q.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(4);
+  __device__ static unsigned load_relaxed(const unsigned* p) {
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
-}
+  __device__ static void raise(unsigned* p) {
+    __hip_atomic_store(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ static uint64_t now() { return __builtin_amdgcn_s_memrealtime(); }
+  __device__ static void pause() { __builtin_amdgcn_s_sleep(4); }
+};
 
 // Pass k writes `out` when (npass - 1 - k) is even, else the workspace, so the
 // last pass writes `out`; pass 0 reads `in`.
@@ -220,26 +206,29 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchParams<Real> p) {
     __syncthreads();
     const int64_t item = uni((int64_t)s_item);
     if (item >= q.nitems) break;
-    const int c = find_chunk(q, item);
+    const int c = worklist::find_chunk(q.chunk_first, q.nchunks, item);
     const int job = uni(q.chunk_job[c]);
     const int pass = uni(q.chunk_pass[c]);
     const int sub = (int)(item - uni(q.chunk_first[c]));
     const BatchJob<Real>& J = p.jobs[job];
     const int variant = uni(J.variant);
     const int tiles = uni(J.tiles);
-    if (wave0) s_ok = (pass == 0 || wait_count(q, q.done + job, (unsigned)pass * (unsigned)tiles)) ? 1 : 0;
+    if (wave0)
+      s_ok = (pass == 0 || worklist::wait_count<DeviceWait>(q.done + job, worklist::need_before(pass, tiles),
+                                                            q.err, q.timeout_ticks))
+                 ? 1
+                 : 0;
     __syncthreads();
     const bool ok = __builtin_amdgcn_readfirstlane(s_ok) != 0;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every wave sees the previous pass
-    unsigned ndone = 1;
+    unsigned ndone = worklist::tiles_per_item(3);  // 3D items: one tile
     constexpr int DT = sizeof(Real) == 8 ? kF64 : kF32;
     if constexpr (SET >= kSingleBase) {
       constexpr int ND = set_ndim(SET), RR = set_r(SET), SH = set_shape(SET);
       constexpr int D = single_depth_c(DT, ND, RR, SH);
       if constexpr (ND == 2) {
-        const int first = 4 * sub;
-        ndone = (unsigned)((tiles - first) < 4 ? (tiles - first) : 4);
-        const int t = first + wid;
+        ndone = worklist::item_tiles(2, tiles, sub);
+        const int t = worklist::tiles_per_item(2) * sub + wid;
         if (ok && t < tiles) {
           Real* hq = (Real*)lds_raw + (size_t)wid * p.hq_stride;
           // (one body for the FP32 radius-3 star, whose registers overflow with two)
@@ -253,9 +242,8 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchParams<Real> p) {
       if (ok && variant == batch_variant(3, 2, kStar))
         run_3d<Real, 2, kStar, aux_depth_c(DT, 3, 2, kStar)>(J, pass, sub, lds_raw);
     } else if (variant < kBatch3DBase) {
-      const int first = 4 * sub;
-      ndone = (unsigned)((tiles - first) < 4 ? (tiles - first) : 4);
-      const int t = first + wid;
+      ndone = worklist::item_tiles(2, tiles, sub);
+      const int t = worklist::tiles_per_item(2) * sub + wid;
       if (ok && t < tiles) {
         Real* hq = (Real*)lds_raw + (size_t)wid * p.hq_stride;
         switch (variant) {

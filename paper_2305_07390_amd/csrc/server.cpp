@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "plan.hpp"
+#include "server_admission.hpp"
 
 using namespace stencil_impl;
 
@@ -105,8 +106,7 @@ struct stencil_server_s {
   std::mutex mu;
   std::condition_variable cv_work;  // new submissions or stop
   std::condition_variable cv_done;  // a request finished
-  std::deque<Request*> queue;
-  std::vector<Request*> resident;  // admitted, not yet collected
+  Admission<Request> adm;  // queue, resident requests, budget and slots
   std::map<uint64_t, std::unique_ptr<Request>> all;
   uint64_t next_ticket = 1;
   double rate = 3.0e11;  // cell-updates per second, running estimate over rounds
@@ -141,22 +141,10 @@ void finish_locked(stencil_server_s* srv, Request* r, RState s, stencil_status e
   }
 }
 
-// Whether the head of the queue can be admitted now. mu held.
-bool admissible_locked(const stencil_server_s* srv) {
-  if (srv->queue.empty()) return false;
-  const Request* r = srv->queue.front();
-  return (int)srv->resident.size() < srv->cfg.max_slots &&
-         srv->st.hbm_in_use + r->need <= srv->cfg.hbm_budget_bytes;
-}
-
 // Admit queued requests in arrival order while a slot and the budget allow;
 // their inputs are copied on the copy stream. Called with srv->mu held.
 void admit_locked(stencil_server_s* srv) {
-  while (!srv->queue.empty()) {
-    Request* r = srv->queue.front();
-    if ((int)srv->resident.size() >= srv->cfg.max_slots) break;
-    if (srv->st.hbm_in_use + r->need > srv->cfg.hbm_budget_bytes) break;
-    srv->queue.pop_front();
+  srv->adm.admit([&](Request* r) {
     const size_t two = 2 * align256(r->bytes);
     hipError_t e = hipMallocFromPoolAsync((void**)&r->dev, two, srv->pool, srv->copy);
     if (e == hipSuccess)
@@ -169,22 +157,22 @@ void admit_locked(stencil_server_s* srv) {
       r->t_done = Clock::now();
       srv->st.failed++;
       srv->cv_done.notify_all();
-      continue;
+      return false;
     }
-    srv->st.hbm_in_use += r->need;
-    srv->st.hbm_peak = std::max(srv->st.hbm_peak, srv->st.hbm_in_use);
     srv->st.admitted++;
-    srv->resident.push_back(r);
     srv->pending_inputs = true;
     // (a T = 0 request also runs in a round: its job is a device copy on the
     // compute stream, ordered after the upload like every other job)
     r->state = RState::kResident;
-  }
+    return true;
+  });
+  srv->st.hbm_in_use = srv->adm.in_use;
+  srv->st.hbm_peak = srv->adm.peak;
   int active = 0;
-  for (Request* r : srv->resident) active += r->state == RState::kResident;
+  for (Request* r : srv->adm.resident) active += r->state == RState::kResident;
   srv->st.active = active;
   srv->st.max_active = std::max(srv->st.max_active, active);
-  srv->st.queued = (int32_t)srv->queue.size();
+  srv->st.queued = (int32_t)srv->adm.queue.size();
 }
 
 void scheduler(stencil_server_s* srv) {
@@ -194,15 +182,13 @@ void scheduler(stencil_server_s* srv) {
     if (srv->stop) break;
     admit_locked(srv);
     std::vector<Request*> round;
-    for (Request* r : srv->resident)
+    for (Request* r : srv->adm.resident)
       if (r->state == RState::kResident) round.push_back(r);
     if (round.empty()) {
       if (srv->stop) break;
-      // Sleep until a queued request fits (a submission, or a collection
-      // that frees a slot and memory). Waiting on "queue not empty" alone
-      // would return at once while the head does not fit, and the loop would
-      // spin holding the lock that submit and collect need.
-      srv->cv_work.wait(lock, [&] { return srv->stop || admissible_locked(srv); });
+      // sleep until a queued request fits (a submission, or a collection
+      // that frees a slot and memory)
+      srv->adm.wait_admissible(srv->cv_work, lock, [&] { return srv->stop; });
       if (srv->stop) break;
       continue;
     }
@@ -291,11 +277,7 @@ void scheduler(stencil_server_s* srv) {
 
 // Give back a collected (or dropped) request's device memory. mu held.
 void release_locked(stencil_server_s* srv, Request* r) {
-  auto it = std::find(srv->resident.begin(), srv->resident.end(), r);
-  if (it != srv->resident.end()) {
-    srv->resident.erase(it);
-    srv->st.hbm_in_use -= r->need;
-  }
+  if (srv->adm.release(r)) srv->st.hbm_in_use = srv->adm.in_use;
   if (r->dev) {
     // the block may still be the target of an admission copy that no round
     // waited for (a request that failed before its first round)
@@ -374,6 +356,8 @@ stencil_status stencil_server_create(const stencil_server_config* config, stenci
   std::unique_ptr<stencil_server_s> srv(new (std::nothrow) stencil_server_s());
   if (!srv) return fail(STENCIL_ERR_NOMEM, "host allocation failed");
   srv->cfg = *config;
+  srv->adm.budget = config->hbm_budget_bytes;
+  srv->adm.slots = config->max_slots;
   if (srv->cfg.quantum_passes <= 0) srv->cfg.quantum_passes = 4;
   if (!(srv->cfg.round_target_s > 0)) srv->cfg.round_target_s = 0.0;
   std::memset(&srv->st, 0, sizeof(srv->st));
@@ -458,10 +442,10 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
     srv->first_submit = r->t_submit;
   }
   *ticket = r->ticket;
-  srv->queue.push_back(r.get());
+  srv->adm.queue.push_back(r.get());
   srv->all[r->ticket] = std::move(r);
   srv->st.submitted++;
-  srv->st.queued = (int32_t)srv->queue.size();
+  srv->st.queued = (int32_t)srv->adm.queue.size();
   srv->cv_work.notify_all();
   return STENCIL_OK;
 }
@@ -505,7 +489,7 @@ stencil_status stencil_server_destroy(stencil_server_t srv) {
   {
     std::lock_guard<std::mutex> lock(srv->mu);
     srv->stop = true;
-    srv->queue.clear();
+    srv->adm.queue.clear();
   }
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
