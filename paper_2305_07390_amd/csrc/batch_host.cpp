@@ -551,6 +551,22 @@ stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stre
   return st;
 }
 
+stencil_status batch_submit_planned(const std::vector<const stencil_plan_s*>& plans,
+                                    const std::vector<int64_t>& steps, const std::vector<const void*>& ins,
+                                    const std::vector<void*>& outs, hipStream_t s, hipMemPool_t pool) {
+  const size_t n = plans.size();
+  std::vector<stencil_plan_s> copies(n);
+  std::vector<stencil_plan_s*> run(n, nullptr);
+  for (size_t i = 0; i < n; ++i) {
+    if (!plans[i]) continue;
+    copies[i] = *plans[i];
+    plan_schedule(&copies[i], steps[i]);
+    run[i] = &copies[i];
+  }
+  std::vector<void*> wsg(n, nullptr);
+  return batch_run(run, ins, outs, wsg, s, pool);
+}
+
 int serve_seg_2d() { return kServeSeg2D; }
 int serve_seg_3d() { return kServeSeg3D; }
 

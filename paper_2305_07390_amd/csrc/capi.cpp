@@ -435,6 +435,41 @@ stencil_status run_naive(const stencil_plan_s* p, const void* in, void* out, voi
 
 }  // namespace
 
+namespace stencil_impl {
+
+// Pass schedule of plan p for T steps (ceil(T / depth) passes, the last one
+// taking the remainder; one step per pass for the plain kernel; none for a
+// copy) and the workspace it needs: one padded grid for the ping-pong when
+// there are two or more passes, plus the halo ring and control words of a
+// device-tiled plan. The tile geometry is T's own business only through the
+// depth, so a plan made for one T serves any other T with this.
+void plan_schedule(stencil_plan_s* p, int64_t T) {
+  p->T = T;
+  if (T == 0) {
+    p->scheme = STENCIL_SCHEME_COPY;
+    p->pass_depth.clear();
+  } else if (p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D ||
+             p->scheme == STENCIL_SCHEME_DEVICE_3D) {
+    const int64_t q = T / p->depth, rem = T % p->depth;
+    p->pass_depth.assign((size_t)q, p->depth);
+    if (rem) p->pass_depth.push_back((int)rem);
+  } else if (p->scheme != STENCIL_SCHEME_COPY) {
+    p->pass_depth.assign((size_t)T, 1);
+  }
+  const size_t bytes = (size_t)p->padded_elems * p->elem;
+  p->workspace = p->pass_depth.size() >= 2 ? bytes : 0;
+  if (p->scheme == STENCIL_SCHEME_DEVICE_3D) {
+    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
+    p->dev_ring_off = align(p->workspace);
+    // each ring cell is stored as (32-bit word, tag) pairs: twice its size
+    p->dev_ring_bytes = (size_t)p->tiles * (size_t)tb3d_dev_ring_elems(p->r, p->depth) * 2 * p->elem;
+    p->dev_ctl_off = align(p->dev_ring_off + p->dev_ring_bytes);
+    p->workspace = p->dev_ctl_off + align(sizeof(unsigned int));
+  }
+}
+
+}  // namespace stencil_impl
+
 extern "C" {
 
 const char* stencil_last_error(void) { return g_last_error.c_str(); }
@@ -616,25 +651,8 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
         }
       }
     }
-    if (p->scheme == STENCIL_SCHEME_BLOCKED_2D || p->scheme == STENCIL_SCHEME_BLOCKED_3D ||
-        p->scheme == STENCIL_SCHEME_DEVICE_3D) {
-      int64_t q = T / p->depth, rem = T % p->depth;
-      p->pass_depth.assign((size_t)q, p->depth);
-      if (rem) p->pass_depth.push_back((int)rem);
-    } else {
-      p->pass_depth.assign((size_t)T, 1);
-    }
   }
-  const size_t bytes = (size_t)p->padded_elems * p->elem;
-  p->workspace = p->pass_depth.size() >= 2 ? bytes : 0;
-  if (p->scheme == STENCIL_SCHEME_DEVICE_3D) {
-    auto align = [](size_t v) { return (v + 255) / 256 * 256; };
-    p->dev_ring_off = align(p->workspace);
-    // each ring cell is stored as (32-bit word, tag) pairs: twice its size
-    p->dev_ring_bytes = (size_t)p->tiles * (size_t)tb3d_dev_ring_elems(p->r, p->depth) * 2 * p->elem;
-    p->dev_ctl_off = align(p->dev_ring_off + p->dev_ring_bytes);
-    p->workspace = p->dev_ctl_off + align(sizeof(unsigned int));
-  }
+  plan_schedule(p, T);
   if (p->scheme == STENCIL_SCHEME_NAIVE && p->tap_off.size() > (size_t)kMaxNaiveTaps) {
     delete p;
     return fail(STENCIL_ERR_UNSUPPORTED, "more than %d non-zero coefficients without a blocked kernel",

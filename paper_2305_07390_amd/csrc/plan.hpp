@@ -40,11 +40,19 @@ stencil_status batch_submit_tiles(const stencil_job* jobs, int32_t n, void* stre
 // the model's, on uniform tiles of seg2d rows / seg3d planes, capped at the
 // fused kernel's depth (a job with no batched variant: a single-grid plan).
 stencil_status plan_batch_job(const stencil_job& j, int seg2d, int seg3d, stencil_plan_s** out);
+// Prepared plans (not owned) run for steps[i] steps each in one batch (a
+// copy of each plan rescheduled with plan_schedule), from ins[i] to outs[i].
+// The plans' memory must not overlap (not checked).
+stencil_status batch_submit_planned(const std::vector<const stencil_plan_s*>& plans,
+                                    const std::vector<int64_t>& steps, const std::vector<const void*>& ins,
+                                    const std::vector<void*>& outs, hipStream_t s, hipMemPool_t pool);
 int serve_seg_2d();
 int serve_seg_3d();
 // The model's machine parameters and its predicted rate of a plan
 // (machine.cpp).
 stencil_machine machine();
+// Pass schedule and workspace of plan p for T steps at its depth (capi.cpp).
+void plan_schedule(stencil_plan_s* p, int64_t T);
 double plan_model_rate(const stencil_plan_s* p);
 // Watchdog limit of in-kernel bounded waits (s_memrealtime ticks), and the
 // per-stream report word that stencil_sync reads (batch_host.cpp).

@@ -72,8 +72,9 @@ class PinnedPool {
 
 struct Request {
   uint64_t ticket = 0;
-  std::vector<double> coeffs;
-  stencil_job job;  // in/out unused; coeffs points into `coeffs`
+  // the batched plan, made once at submit; each round runs a copy
+  // rescheduled for its steps
+  std::unique_ptr<stencil_plan_s> plan;
   void* host_in = nullptr;  // pinned copy of the input (released after the first round)
   size_t host_cls = 0;
   size_t bytes = 0;  // one padded grid
@@ -194,7 +195,9 @@ void scheduler(stencil_server_s* srv) {
     }
     // one quantum of every resident request, in one batched launch: each
     // request's fair share of the round's work, in whole passes
-    std::vector<stencil_job> jobs(round.size());
+    std::vector<const stencil_plan_s*> plans(round.size());
+    std::vector<const void*> ins(round.size());
+    std::vector<void*> outs(round.size());
     std::vector<int64_t> steps(round.size());
     const double share = srv->cfg.round_target_s > 0
                              ? srv->cfg.round_target_s * srv->rate / (double)round.size()
@@ -206,11 +209,9 @@ void scheduler(stencil_server_s* srv) {
       q = std::max<int64_t>(q, (int64_t)srv->cfg.quantum_passes * r->depth);
       steps[k] = std::min(r->remaining, q);
       round_updates += (double)steps[k] * (double)r->cells;
-      jobs[k] = r->job;
-      jobs[k].T = steps[k];
-      jobs[k].in = r->grid(r->cur);
-      jobs[k].out = r->grid(1 - r->cur);
-      jobs[k].tag = r->ticket;
+      plans[k] = r->plan.get();
+      ins[k] = r->grid(r->cur);
+      outs[k] = r->grid(1 - r->cur);
     }
     const bool wait_inputs = srv->pending_inputs;
     srv->pending_inputs = false;
@@ -221,11 +222,8 @@ void scheduler(stencil_server_s* srv) {
           hipStreamWaitEvent(srv->compute, srv->inputs_ready, 0) != hipSuccess)
         st = hip_fail(hipErrorUnknown, "server input ordering");
     }
-    std::vector<stencil_status> js(round.size(), STENCIL_OK);
     const Clock::time_point t0 = Clock::now();
-    if (st == STENCIL_OK)
-      st = batch_submit_tiles(jobs.data(), (int32_t)jobs.size(), srv->compute, js.data(), serve_seg_2d(),
-                              serve_seg_3d(), srv->pool);
+    if (st == STENCIL_OK) st = batch_submit_planned(plans, steps, ins, outs, srv->compute, srv->pool);
     if (st == STENCIL_OK && hipEventRecord(srv->round_end, srv->compute) != hipSuccess)
       st = hip_fail(hipErrorUnknown, "server round event");
     // while the round runs, admit arrivals so their inputs are on the device
@@ -263,8 +261,8 @@ void scheduler(stencil_server_s* srv) {
         srv->pinned.put(r->host_in, r->host_cls);
         r->host_in = nullptr;
       }
-      if (st != STENCIL_OK || js[k] != STENCIL_OK) {
-        finish_locked(srv, r, RState::kFailed, st != STENCIL_OK ? st : js[k]);
+      if (st != STENCIL_OK) {
+        finish_locked(srv, r, RState::kFailed, st);
         continue;
       }
       r->cur = 1 - r->cur;
@@ -418,19 +416,13 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
   r->updates = (double)pl->cells * (double)job->T;
   r->depth = pl->scheme == STENCIL_SCHEME_NAIVE ? 1 : std::max(1, pl->depth);
   r->cells = std::max<int64_t>(1, pl->cells);
-  r->coeffs = pl->coeffs;
-  stencil_plan_destroy(pl);
+  r->plan.reset(pl);
   if (r->need > srv->cfg.hbm_budget_bytes) {
     std::lock_guard<std::mutex> lock(srv->mu);
     srv->st.rejected++;
     return fail(STENCIL_ERR_BUDGET, "request needs %zu bytes of device memory; the budget is %llu",
                 r->need, (unsigned long long)srv->cfg.hbm_budget_bytes);
   }
-  r->job = *job;
-  r->job.coeffs = r->coeffs.data();
-  r->job.in = nullptr;
-  r->job.out = nullptr;
-  r->job.depth = r->depth;
   r->host_in = srv->pinned.get(r->bytes, &r->host_cls);
   if (!r->host_in) return fail(STENCIL_ERR_NOMEM, "pinned staging of %zu bytes failed", r->bytes);
   std::memcpy(r->host_in, host_in, r->bytes);
