@@ -100,6 +100,47 @@ def build(jobs: int | None = None, verbose: bool = True, only: list | None = Non
     return LIB
 
 
+# Ablation variants (paper Section 7, breakdown study): the library with
+# some kernel optimisations compiled out (the STENCIL_ABL_* switches of
+# tb2d_impl.hpp and tb3d_impl.hpp). Only the named sources are recompiled;
+# every other object comes from the default build, which must exist.
+VARIANTS = os.path.join(HERE, "ablation_builds")
+
+
+def build_variant(name: str, defines: dict, only: list, verbose: bool = True) -> str:
+    objdir = os.path.join(BUILD, "abl_" + name)
+    os.makedirs(objdir, exist_ok=True)
+    outdir = os.path.join(VARIANTS, name)
+    os.makedirs(outdir, exist_ok=True)
+    flags = [f"-D{k}={v}" for k, v in sorted(defines.items())]
+    objs = []
+    for src in sources():
+        base = os.path.basename(src)
+        if base in only:
+            obj = os.path.join(objdir, base + ".o")
+            cmd = [_hipcc(), *COMMON, *DEVICE_FLAGS, *flags, "-Rpass-analysis=kernel-resource-usage", "-c", src,
+                   "-o", obj]
+            res = subprocess.run(cmd, capture_output=True, text=True)
+            if res.returncode != 0:
+                raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+            spills = [n for n, r in _resources(res.stderr) if r.get("ScratchSize") not in ("0", None)]
+            if spills:
+                raise RuntimeError(f"variant {name}: kernels spill to scratch: {spills}")
+        else:
+            obj = os.path.join(BUILD, base + ".o")
+            if not os.path.exists(obj):
+                raise RuntimeError(f"{obj} missing: build the library first")
+        objs.append(obj)
+    lib = os.path.join(outdir, "libstencil.so")
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", lib, *objs]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    if verbose:
+        print(f"built {lib} ({', '.join(flags)})", file=sys.stderr)
+    return lib
+
+
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser()

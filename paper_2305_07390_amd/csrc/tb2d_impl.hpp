@@ -49,6 +49,28 @@
 #include "device_common.hpp"
 #include "launch.hpp"
 
+// Ablation switches (paper Section 7, breakdown study): each names one
+// optimisation of this kernel. The library is built with every one on (the
+// defaults); paper_2305_07390_amd/ablation.py builds variants with some off to
+// measure what each is worth.
+//   STENCIL_ABL_PREFETCH       level-0 rows are loaded ahead of their use into
+//                              a register ring (0: each row is loaded when used)
+//   STENCIL_ABL_SCHED_BARRIER  each row's prefetch stays at the head of its row
+//   STENCIL_ABL_SPLIT_BODY     interior strips run a tile body without halo reads
+//   STENCIL_ABL_XCD_ORDER      each XCD runs a run of consecutive tile groups
+#ifndef STENCIL_ABL_PREFETCH
+#define STENCIL_ABL_PREFETCH 1
+#endif
+#ifndef STENCIL_ABL_SCHED_BARRIER
+#define STENCIL_ABL_SCHED_BARRIER 1
+#endif
+#ifndef STENCIL_ABL_SPLIT_BODY
+#define STENCIL_ABL_SPLIT_BODY 1
+#endif
+#ifndef STENCIL_ABL_XCD_ORDER
+#define STENCIL_ABL_XCD_ORDER 1
+#endif
+
 namespace stencil_impl {
 using namespace stencil_dev;
 
@@ -111,7 +133,7 @@ template <int R>
 struct Ring0 {
   // level-0 row slots: prefetch distance + 1, chosen so the rotation period
   // lcm(2r, slots) stays short
-  static constexpr int value = (2 * R >= 4) ? 2 * R : 4;
+  static constexpr int value = !STENCIL_ABL_PREFETCH ? 1 : (2 * R >= 4) ? 2 * R : 4;
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -233,7 +255,7 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
     // keep the prefetch at the head of its row: the scheduler otherwise sinks
     // the loads of an unrolled iteration towards its end, and the next
     // iteration then waits on all of them (vmcnt also counts the stores)
-    if (!GENERAL) __builtin_amdgcn_sched_barrier(0);
+    if (!GENERAL && STENCIL_ABL_SCHED_BARRIER) __builtin_amdgcn_sched_barrier(0);
   }
   Real x[V];
 #pragma unroll
@@ -412,7 +434,7 @@ __device__ __forceinline__ void tb2d_tile(const Real* __restrict__ w, const void
                                           const int lane, const int edge, const int X0,
                                           const int la, const int lb, const int Y0, const int Y1,
                                           const int d) {
-  if (edge == kInterior)
+  if (edge == kInterior && STENCIL_ABL_SPLIT_BODY)
     tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, false>(w, src, dst, orig, P, Q, hq, lane, edge, X0, la,
                                                     lb, Y0, Y1, d);
   else
@@ -439,7 +461,7 @@ __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
   // other's margin columns, share an L2 (a bijection for any grid size).
   const int g = (int)gridDim.x, xcd = (int)blockIdx.x % 8, slot = (int)blockIdx.x / 8;
   const int per = g / 8, extra = g % 8;
-  const int swz = xcd * per + (xcd < extra ? xcd : extra) + slot;
+  const int swz = STENCIL_ABL_XCD_ORDER ? xcd * per + (xcd < extra ? xcd : extra) + slot : (int)blockIdx.x;
   for (int tile = swz * waves + wid; tile < a.ntiles; tile += stride) {
     const Tile2D g = locate_2d(tile, ns, a.seg_len, a.seg_len_e, a.edge_tiles, P, Q, R, V, HL);
     tb2d_tile<Real, R, SHAPE, DEPTH, V>(a.w, a.src, a.dst, a.orig, P, Q, hq, lane, g.edge, g.X0,

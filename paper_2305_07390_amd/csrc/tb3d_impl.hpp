@@ -126,10 +126,23 @@ struct Lds {
 // rings hide more HBM latency (one workgroup per CU has little else to hide
 // it with); FP64 star and box variants at depth 2 keep 2, the most their
 // registers allow without spilling.
-constexpr int plane_ring(bool f64, int r, int shape, int depth) {
+//
+// Ablation switch (paper Section 7, breakdown study; see
+// paper_2305_07390_amd/ablation.py): STENCIL_ABL_PLANES caps the planes in
+// flight (at least 2, one plane ahead: the ring also carries the face values
+// of the next plane).
+#ifndef STENCIL_ABL_PLANES
+#define STENCIL_ABL_PLANES 4
+#endif
+static_assert(STENCIL_ABL_PLANES >= 2, "the plane ring holds at least the next plane");
+constexpr int plane_ring_full(bool f64, int r, int shape, int depth) {
   if (!f64 || shape == kGeneral) return 4;
   if (shape == kStar) return (r == 1 || depth == 1) ? 4 : 2;
   return 2;
+}
+constexpr int plane_ring(bool f64, int r, int shape, int depth) {
+  return plane_ring_full(f64, r, shape, depth) < STENCIL_ABL_PLANES ? plane_ring_full(f64, r, shape, depth)
+                                                                     : STENCIL_ABL_PLANES;
 }
 
 template <typename Real, int R, int DEPTH, int Z0_, int BY>

@@ -201,11 +201,14 @@ _SIGNATURES = {
 _lib = None
 
 
-def load_library(path: str = LIB_PATH):
-    """Load the HIP library; raises StencilLibraryMissing if it was not built."""
+def load_library(path: str | None = None):
+    """Load the HIP library; raises StencilLibraryMissing if it was not built.
+    The path is `path`, else $STENCIL_LIBRARY (another build of the same
+    library, e.g. an ablation variant), else the in-tree build."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("STENCIL_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise StencilLibraryMissing(
             f"{path} not found: build it with `python -m paper_2305_07390_amd.build`")
