@@ -18,7 +18,8 @@
  *   coefficients; the caller may free them on return. Single-precision plans
  *   round every coefficient to float (nearest even) once.
  * Summation: each cell adds its terms in that dense-box order, starting from
- *   +0.0, with one fused multiply-add per term.
+ *   +0.0, with one fused multiply-add per term. A box with no non-zero entry
+ *   is a stencil of no points: every step sets the interior to +0.0.
  * Arrays: `in` and `out` are device pointers (caller-owned, never freed or
  *   retained) to contiguous padded arrays of extents n_j + 2r per dimension,
  *   slowest first, x fastest, in the plan's dtype. `in` is never written.

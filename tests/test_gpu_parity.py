@@ -127,6 +127,18 @@ def test_r0_and_T0():
     assert np.array_equal(got, u1)
 
 
+def test_all_zero_box():
+    # no points: every step sets the interior to the empty sum, +0.0; the halo stays
+    for shape, r in (((40, 300), 1), ((9, 20, 70), 2)):
+        w = np.zeros((2 * r + 1,) * len(shape))
+        u0 = wl.make_field(shape, r, 86)
+        info = _check(w, r, u0, 3)
+        assert info["points"] == 0
+        got = gpu_sweep(w, r, u0, 3)
+        inner = tuple(slice(r, -r) for _ in shape)
+        assert np.all(got[inner] == 0.0) and not np.any(np.signbit(got[inner]))
+
+
 def test_3d_small_plain():
     for kind, r in (("star", 1), ("box", 1), ("star", 2)):
         w = wl.poisson_like_coeffs(3, kind, r, 84)
