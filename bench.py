@@ -581,7 +581,10 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
         sweep.append({"rate": srate, "requests": n_s, "offered_gcells_per_s": round(woff / 1e9, 1),
                       "served_gcells_per_s": round(ws["cell_updates"] / max(ws["wall_s"], 1e-9) / 1e9, 1),
                       "p50_ms": round(float(np.percentile(wl_, 50)) * 1e3, 2),
-                      "p99_ms": round(float(np.percentile(wl_, 99)) * 1e3, 2)})
+                      "p99_ms": round(float(np.percentile(wl_, 99)) * 1e3, 2),
+                      # the driver's lateness in submitting: the host staging of
+                      # the inputs bounds the load that reaches the server
+                      "submit_lag_ms": round(float(wres["submit_lag_s"]) * 1e3, 1)})
         log(f"  serving sweep {sweep[-1]}")
     # stress: small budget, twice the rate, so admission binds
     sreqs, sarr = workloads.serving_requests(400, rate_hz=2 * rate, seed=9, dtype=np.float32)

@@ -70,6 +70,36 @@ class PinnedPool {
   std::multimap<size_t, void*> free_;
 };
 
+// Host copy of a request's grid into or out of pinned staging. One thread
+// copies at about 7 GB/s, so a 13 MB grid takes about 2 ms of the caller's
+// submit or wait: under load that, not the device, bounded the requests a
+// client could put through. Large copies are split over a few threads.
+void staging_copy(void* dst, const void* src, size_t bytes) {
+  constexpr size_t kSplit = (size_t)4 << 20;  // below this one thread copies
+  constexpr int kThreads = 4;
+  if (bytes < kSplit) {
+    std::memcpy(dst, src, bytes);
+    return;
+  }
+  const size_t part = (bytes / kThreads + 4095) / 4096 * 4096;
+  std::thread helpers[kThreads - 1];
+  int started = 0;
+  for (int k = 1; k < kThreads; ++k) {
+    const size_t off = (size_t)k * part;
+    if (off >= bytes) break;
+    const size_t len = std::min(part, bytes - off);
+    try {
+      helpers[started] = std::thread(
+          [=] { std::memcpy((char*)dst + off, (const char*)src + off, len); });
+      ++started;
+    } catch (...) {  // no thread: copy this part here
+      std::memcpy((char*)dst + off, (const char*)src + off, len);
+    }
+  }
+  std::memcpy(dst, src, std::min(part, bytes));
+  for (int k = 0; k < started; ++k) helpers[k].join();
+}
+
 struct Request {
   uint64_t ticket = 0;
   // the batched plan, made once at submit; each round runs a copy
@@ -326,7 +356,7 @@ stencil_status collect(stencil_server_s* srv, uint64_t ticket, void* host_out, b
       } else {
         e = hipMemcpyAsync(bounce, src, bytes, hipMemcpyDeviceToHost, srv->collect);
         if (e == hipSuccess) e = hipStreamSynchronize(srv->collect);
-        if (e == hipSuccess) std::memcpy(host_out, bounce, bytes);
+        if (e == hipSuccess) staging_copy(host_out, bounce, bytes);
         srv->pinned.put(bounce, cls);
       }
     }
@@ -425,7 +455,7 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
   }
   r->host_in = srv->pinned.get(r->bytes, &r->host_cls);
   if (!r->host_in) return fail(STENCIL_ERR_NOMEM, "pinned staging of %zu bytes failed", r->bytes);
-  std::memcpy(r->host_in, host_in, r->bytes);
+  staging_copy(r->host_in, host_in, r->bytes);
   std::lock_guard<std::mutex> lock(srv->mu);
   r->ticket = srv->next_ticket++;
   r->t_submit = t_call;
