@@ -45,6 +45,11 @@ HBM_PEAK_GBS = 8000.0
 FP64_VALU_TFLOPS = 78.6
 # FP32 as built: packed FP32 is not used, so FP32 FMAs issue at the FP64 rate
 FP32_VALU_TFLOPS = 78.6
+# resident requests of the serving runs: a round's work list holds one quantum
+# of each, and with 64 the rounds of a loaded server had too few items to fill
+# the device (served FP32 422 GCells/s at 1600 req/s against 630 with 256);
+# at 200 req/s fewer than 20 are ever resident
+SERVE_SLOTS = 256
 
 
 def log(msg):
@@ -535,7 +540,7 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
     def keep(k, res):
         if k in sample:
             kept[k] = res
-    with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=64) as srv:
+    with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=SERVE_SLOTS) as srv:
         res = serving.serve_open_loop(srv, reqs, arr, on_result=keep)
     # latency from each request's scheduled arrival (the driver's lag to the
     # submit call included) to the end of the round that completes it
@@ -573,7 +578,7 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
     for k, srate in enumerate((400.0, 800.0, 1600.0)):
         n_s = int(srate * 1.0)
         wreqs, warr = workloads.serving_requests(n_s, rate_hz=srate, seed=20 + k, dtype=np.float32)
-        with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=64) as srv:
+        with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=SERVE_SLOTS) as srv:
             wres = serving.serve_open_loop(srv, wreqs, warr)
         ws = wres["stats"]
         wl_ = np.array(wres["arrival_latency_s"])
@@ -593,7 +598,8 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
     ss = sres["stats"]
     slat = np.array(sres["arrival_latency_s"])
     out = {"workload": f"Poisson arrivals {rate:g} req/s, {warmup} warm-up + {measured} measured requests, "
-                       "grids drawn like the batch (pool of 32), FP32, 200 GB HBM budget",
+                       "grids drawn like the batch (pool of 32), FP32, 200 GB HBM budget, "
+                       f"{SERVE_SLOTS} slots",
            "requests": count, "completed": s["completed"], "rejected": len(res["rejected"]),
            "offered_gcells_per_s": round(offered / 1e9, 1),
            "throughput_gcells_per_s": round(s["cell_updates"] / max(s["wall_s"], 1e-9) / 1e9, 1),
