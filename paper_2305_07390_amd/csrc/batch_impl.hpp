@@ -69,9 +69,11 @@ __device__ __forceinline__ void pass_buffers(const void* in, void* out, void* ws
 // Deepest compiled depth of a batched variant (0: not in the batch kernel;
 // such jobs run with their single-grid kernels after it). All variants share
 // one kernel, and so one register allocation, where some tiles spill at their
-// single-grid depth: 2D radius-2 stars stop at 7 (FP64) and 6 (FP32), and
-// FP64 3D radius-2 tiles (4 x 2 cells per lane) are left out.
+// single-grid depth: 2D radius-2 stars stop at 7 (FP64) and 6 (FP32),
+// radius-3 stars at 4, and FP64 3D radius-2 tiles (4 x 2 cells per lane) are
+// left out.
 constexpr int batch_depth_c(int dtype, int ndim, int r, int shape) {
+  if (ndim == 2 && r == 3 && shape == kStar) return 4;
   if (ndim == 2) return (r == 2 && shape == kStar) ? (dtype == kF64 ? 7 : 6) : max_depth_c(r, shape);
   if (dtype == kF64 && r == 2) return 0;
   return tb3d::max_depth_c(dtype, r, shape);
@@ -168,10 +170,11 @@ constexpr int set_r(int set) { return ((set - kSingleBase) % kBatch3DBase) / 3 +
 constexpr int set_shape(int set) { return (set - kSingleBase) % 3; }
 // Depth and plane ring of a single-variant kernel: the single-grid ones,
 // except where the job descriptor's extra registers would spill (2D radius-2
-// stars stop at 7 / 6 as in the fused kernel; the FP64 3D 7-point star keeps
-// two planes in flight).
+// stars stop at 7 / 6 and radius-3 stars at 4 as in the fused kernel; the
+// FP64 3D 7-point star keeps two planes in flight).
 constexpr int single_depth_c(int dtype, int ndim, int r, int shape) {
   if (ndim == 2 && r == 2 && shape == kStar) return dtype == kF64 ? 7 : 6;
+  if (ndim == 2 && r == 3 && shape == kStar) return 4;
   return ndim == 2 ? max_depth_c(r, shape) : tb3d::max_depth_c(dtype, r, shape);
 }
 constexpr int single_ring_c(int dtype, int r, int shape, int depth) {

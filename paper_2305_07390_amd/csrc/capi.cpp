@@ -58,7 +58,7 @@ DeviceInfo device_info() {
 
 namespace {
 
-constexpr int64_t kLdsBudget = 64 * 1024;
+constexpr int64_t kLdsBudget = 128 * 1024;
 
 bool classify(int ndim, int r, const double* c, int* pattern, int* points) {
   const int side = 2 * r + 1;
@@ -117,7 +117,8 @@ void plan_2d_tiles(stencil_plan_s* p, int depth, int seg_hint, int cus, bool edg
   const int64_t row_bytes = p->ext[2] * (int64_t)p->elem;
   const int64_t max_rows = ((int64_t)1 << 31) / row_bytes - 2 * depth * p->r - 16;
   if (seg > max_rows) seg = (int)std::max<int64_t>(1, max_rows);
-  // the per-wave LDS halo queue (4 waves x rows x 2r values) stays within 64 KB
+  // the per-wave LDS halo queue (4 waves x rows x 2r values) stays within
+  // 128 KB of the CU's 160 KB (the launch raises the kernel's LDS limit)
   const int64_t lds_rows = kLdsBudget / (4 * 2 * p->r * (int64_t)p->elem) - 2 * depth * p->r - 8;
   if (seg > lds_rows) seg = (int)std::max<int64_t>(1, lds_rows);
   if (seg > Q) seg = (int)Q;

@@ -474,7 +474,7 @@ __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
 // values per lane). The general pattern (runtime zero skipping) is a fallback;
 // for r >= 3 it has no blocked variant.
 constexpr int max_depth_c(int r, int shape) {
-  if (shape == kStar) return r == 1 ? 12 : r == 2 ? 8 : r == 3 ? 4 : 2;
+  if (shape == kStar) return r == 1 ? 12 : r == 2 ? 8 : r == 3 ? 5 : 2;
   if (shape == kBox) return r == 1 ? 8 : r == 2 ? 5 : r == 3 ? 3 : 2;
   return r == 1 ? 3 : r == 2 ? 2 : 0;
 }
@@ -486,9 +486,14 @@ hipError_t launch_depth(int depth, const Tb2dParams<Real>* p, int grid, int bloc
     return hipErrorInvalidValue;
   } else {
     if (depth == D) {
+      const void* fn = (const void*)&tb2d_kernel<Real, R, SHAPE, D>;
+      // the edge strips' halo queues may take more than the default 64 KB
+      if (lds > (size_t)64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+      }
       void* args[] = {(void*)p};
-      return hipLaunchKernel((const void*)&tb2d_kernel<Real, R, SHAPE, D>, dim3(grid), dim3(block),
-                             args, lds, s);
+      return hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, s);
     }
     return launch_depth<Real, R, SHAPE, D - 1>(depth, p, grid, block, lds, s);
   }

@@ -53,7 +53,7 @@ def test_machine_set_validates_and_resets():
 
 # (workload, stencil index, expected scheme, expected depth); the depths are
 # the fastest measured on the MI355X for these sizes
-SUITE_2D_PICKS = [(0, 12), (1, 8), (2, 4), (3, 5)]
+SUITE_2D_PICKS = [(0, 12), (1, 8), (2, 5), (3, 5)]
 SUITE_3D_PICKS = [(0, 4), (1, 2), (2, 2)]
 
 
@@ -174,18 +174,27 @@ def test_shared_3d_tiles_plan_like_a_full_device():
     assert alone["depth"] < shared["depth"] == full["depth"]
 
 
+# depth caps of the fused batch kernel below the single-grid ones (its one
+# register allocation for every variant): 2D radius-2 stars 7 / 6 (FP64 /
+# FP32), 2D radius-3 stars 4
+BATCH_CAPS = {(2, "star", 2): {np.float64: 7, np.float32: 6}, (2, "star", 3): {np.float64: 4, np.float32: 4}}
+
+
 def test_batch_describe_reports_the_batched_plan():
     # the 128-grid batch: every job planned as the batch runs it, never
-    # shallower than the same grid planned alone, and never device-tiled
+    # shallower than the same grid planned alone (within the fused kernel's
+    # caps), and never device-tiled
     probs = wl.batch_problems()
     deeper = 0
     for p in probs:
         for dt in (np.float64, np.float32):
             info = st.stencil_batch_describe(p.coeffs, p.spec.r, p.interior, dt, p.T)
             alone = _plan(p.spec, p.interior, dt, p.T, seed=0)
+            cap = BATCH_CAPS.get((p.spec.ndim, p.spec.kind, p.spec.r), {}).get(dt, 99)
             assert info["scheme_name"] in ("blocked_2d", "blocked_3d")
             assert info["passes"] == -(-p.T // info["depth"])
-            assert info["depth"] >= alone["depth"] or p.T < alone["depth"]
+            assert info["depth"] <= cap
+            assert info["depth"] >= min(alone["depth"], cap) or p.T < alone["depth"]
             deeper += info["depth"] > alone["depth"]
     assert deeper > len(probs) // 2
     with pytest.raises(st.StencilError):
