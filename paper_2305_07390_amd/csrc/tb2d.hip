@@ -32,7 +32,7 @@ hipError_t launch_r(int r, int shape, int depth, const Tb2dParams<Real>* p, int 
 
 hipError_t tb2d_launch(int dtype, int r, int shape, int depth, const void* params, int grid,
                        int block, size_t lds_bytes, hipStream_t stream) {
-  if (depth < 1 || depth > max_depth_c(r, shape)) return hipErrorInvalidValue;
+  if (depth < 1 || depth > max_depth_c(dtype == kF64, r, shape)) return hipErrorInvalidValue;
   if (dtype == kF64)
     return launch_r<double>(r, shape, depth, (const Tb2dParams<double>*)params, grid, block,
                             lds_bytes, stream);
@@ -43,9 +43,8 @@ hipError_t tb2d_launch(int dtype, int r, int shape, int depth, const void* param
 }
 
 int tb2d_max_depth(int dtype, int r, int shape) {
-  (void)dtype;
   if (r < 1 || r > kMaxR || shape < kStar || shape > kGeneral) return 0;
-  return max_depth_c(r, shape);
+  return max_depth_c(dtype == kF64, r, shape);
 }
 
 int tb2d_cols_per_lane(int dtype, int r, int shape) { return tb2d_cols(dtype == kF64, r, shape); }

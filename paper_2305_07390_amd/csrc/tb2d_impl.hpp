@@ -469,13 +469,15 @@ __global__ __launch_bounds__(256) void tb2d_kernel(const Tb2dParams<Real> a) {
   }
 }
 
-// Deepest compiled variant per (radius, shape): the deepest that compiles
-// without scratch spills on gfx950 (each level holds 2r partial rows of V
-// values per lane). The general pattern (runtime zero skipping) is a fallback;
-// for r >= 3 it has no blocked variant.
-constexpr int max_depth_c(int r, int shape) {
+// Deepest compiled variant per (dtype, radius, shape): at most the deepest
+// that compiles without scratch spills on gfx950 (each level holds 2r partial
+// rows of V values per lane), and no deeper than the deepest that still runs
+// faster where the levels past the VGPRs live in AGPRs (measured at 8192^2:
+// the radius-1 star stops at 12, the radius-3 star at 5). The general pattern
+// (runtime zero skipping) is a fallback; for r >= 3 it has no blocked variant.
+constexpr int max_depth_c(bool f64, int r, int shape) {
   if (shape == kStar) return r == 1 ? 12 : r == 2 ? 8 : r == 3 ? 5 : 2;
-  if (shape == kBox) return r == 1 ? 8 : r == 2 ? 5 : r == 3 ? 3 : 2;
+  if (shape == kBox) return r == 1 ? 10 : r == 2 ? (f64 ? 6 : 5) : r == 3 ? 3 : 2;
   return r == 1 ? 3 : r == 2 ? 2 : 0;
 }
 
@@ -506,11 +508,12 @@ hipError_t tb2d_launch_r(int shape, int depth, const Tb2dParams<Real>* p, int gr
                          size_t lds, hipStream_t s) {
   switch (shape) {
     case kStar:
-      return launch_depth<Real, R, kStar, max_depth_c(R, kStar)>(depth, p, grid, block, lds, s);
+      return launch_depth<Real, R, kStar, max_depth_c(sizeof(Real) == 8, R, kStar)>(depth, p, grid, block, lds, s);
     case kBox:
-      return launch_depth<Real, R, kBox, max_depth_c(R, kBox)>(depth, p, grid, block, lds, s);
+      return launch_depth<Real, R, kBox, max_depth_c(sizeof(Real) == 8, R, kBox)>(depth, p, grid, block, lds, s);
     case kGeneral:
-      return launch_depth<Real, R, kGeneral, max_depth_c(R, kGeneral)>(depth, p, grid, block, lds, s);
+      return launch_depth<Real, R, kGeneral, max_depth_c(sizeof(Real) == 8, R, kGeneral)>(depth, p, grid, block,
+                                                                                        lds, s);
     default:
       return hipErrorInvalidValue;
   }

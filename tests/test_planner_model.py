@@ -53,7 +53,7 @@ def test_machine_set_validates_and_resets():
 
 # (workload, stencil index, expected scheme, expected depth); the depths are
 # the fastest measured on the MI355X for these sizes
-SUITE_2D_PICKS = [(0, 12), (1, 8), (2, 5), (3, 5)]
+SUITE_2D_PICKS = [(0, 12), (1, 10), (2, 5), (3, 6)]
 SUITE_3D_PICKS = [(0, 4), (1, 2), (2, 2)]
 
 
@@ -176,8 +176,9 @@ def test_shared_3d_tiles_plan_like_a_full_device():
 
 # depth caps of the fused batch kernel below the single-grid ones (its one
 # register allocation for every variant): 2D radius-2 stars 7 / 6 (FP64 /
-# FP32), 2D radius-3 stars 4
-BATCH_CAPS = {(2, "star", 2): {np.float64: 7, np.float32: 6}, (2, "star", 3): {np.float64: 4, np.float32: 4}}
+# FP32), 2D radius-3 stars 4, 2D radius-1 and -2 boxes 8 and 5
+BATCH_CAPS = {(2, "star", 2): {np.float64: 7, np.float32: 6}, (2, "star", 3): {np.float64: 4, np.float32: 4},
+              (2, "box", 1): {np.float64: 8, np.float32: 8}, (2, "box", 2): {np.float64: 5, np.float32: 5}}
 
 
 def test_batch_describe_reports_the_batched_plan():
