@@ -66,12 +66,11 @@ __device__ __forceinline__ void pass_buffers(const void* in, void* out, void* ws
   *dst = ((npass - 1 - pass) & 1) == 0 ? out : ws;
 }
 
-// 2D depths of the persistent kernels (the fused batch kernels and the
-// single-variant ones): their tiles carry a job descriptor's extra registers,
-// so where the single-grid kernels go deeper into the AGPRs these stop at the
-// depths measured and spill-checked for them: radius-2 stars 7 (FP64) / 6
-// (FP32), radius-3 stars 4, radius-1 and -2 boxes 8 and 5.
-constexpr int persistent_2d_depth_c(int dtype, int r, int shape) {
+// 2D depths of the fused batch kernels: every variant shares one register
+// allocation, so where the single-grid kernels go deeper into the AGPRs
+// these stop at the depths measured and spill-checked for it: radius-2 stars
+// 7 (FP64) / 6 (FP32), radius-3 stars 4, radius-1 and -2 boxes 8 and 5.
+constexpr int batch_2d_depth_c(int dtype, int r, int shape) {
   if (shape == kStar) return r == 1 ? 12 : r == 2 ? (dtype == kF64 ? 7 : 6) : r == 3 ? 4 : 2;
   if (shape == kBox) return r == 1 ? 8 : r == 2 ? 5 : r == 3 ? 3 : 2;
   return max_depth_c(dtype == kF64, r, shape);
@@ -79,11 +78,10 @@ constexpr int persistent_2d_depth_c(int dtype, int r, int shape) {
 
 // Deepest compiled depth of a batched variant (0: not in the batch kernel;
 // such jobs run with their single-grid kernels after it). All variants share
-// one kernel, and so one register allocation: 2D tiles take the persistent
-// depths above, and FP64 3D radius-2 tiles (4 x 2 cells per lane) are left
-// out.
+// one kernel, and so one register allocation: 2D tiles take the depths
+// above, and FP64 3D radius-2 tiles (4 x 2 cells per lane) are left out.
 constexpr int batch_depth_c(int dtype, int ndim, int r, int shape) {
-  if (ndim == 2) return persistent_2d_depth_c(dtype, r, shape);
+  if (ndim == 2) return batch_2d_depth_c(dtype, r, shape);
   if (dtype == kF64 && r == 2) return 0;
   return tb3d::max_depth_c(dtype, r, shape);
 }
@@ -177,11 +175,12 @@ constexpr int kSingleBase = 2;
 constexpr int set_ndim(int set) { return 2 + (set - kSingleBase) / kBatch3DBase; }
 constexpr int set_r(int set) { return ((set - kSingleBase) % kBatch3DBase) / 3 + 1; }
 constexpr int set_shape(int set) { return (set - kSingleBase) % 3; }
-// Depth and plane ring of a single-variant kernel: in 2D the persistent
-// depths above (as in the fused kernel), in 3D the single-grid ones, except
-// that the FP64 3D 7-point star keeps two planes in flight.
+// Depth and plane ring of a single-variant kernel: the single-grid ones,
+// except where the job descriptor's extra registers would spill (2D radius-2
+// stars stop at 7 / 6; the FP64 3D 7-point star keeps two planes in flight).
 constexpr int single_depth_c(int dtype, int ndim, int r, int shape) {
-  return ndim == 2 ? persistent_2d_depth_c(dtype, r, shape) : tb3d::max_depth_c(dtype, r, shape);
+  if (ndim == 2 && r == 2 && shape == kStar) return dtype == kF64 ? 7 : 6;
+  return ndim == 2 ? max_depth_c(dtype == kF64, r, shape) : tb3d::max_depth_c(dtype, r, shape);
 }
 constexpr int single_ring_c(int dtype, int r, int shape, int depth) {
   return (dtype == kF64 && r == 1 && shape == kStar && depth == 4) ? 2
