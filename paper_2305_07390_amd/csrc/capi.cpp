@@ -565,7 +565,8 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
       const int V = tb2d_cols_per_lane(dtype, radius, p->pattern);
       const int maxd = tb2d_max_depth(dtype, radius, p->pattern);
       int lo = 1, hi = maxd;
-      if (hint_depth > 0) lo = hi = std::min(hint_depth, maxd);
+      // (a variant without a blocked kernel, maxd = 0, has no candidate)
+      if (hint_depth > 0 && maxd >= 1) lo = hi = std::min(hint_depth, maxd);
       for (int depth = lo; depth <= hi && (int64_t)depth <= T; ++depth) {
         // every strip must lie inside the interior, and its edge redundancy fit in the wave
         const int HL = (depth * radius + V - 1) / V;
@@ -597,6 +598,10 @@ stencil_status stencil_plan(stencil_plan_t* out_plan, const double* coeffs, int3
         *lo = 1;
         *hi = (int)std::min<int64_t>(maxd, T);
         if (hint_depth > 0) *lo = *hi = (int)std::min<int64_t>(std::min(hint_depth, maxd), T);
+        if (*lo < 1) {  // no blocked kernel for this variant: no candidate
+          *lo = 1;
+          *hi = 0;
+        }
       };
       int lo, hi;
       // device tiling: non-overlapping tiles exchanging edges every z-step

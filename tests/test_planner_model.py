@@ -200,3 +200,29 @@ def test_batch_describe_reports_the_batched_plan():
     assert deeper > len(probs) // 2
     with pytest.raises(st.StencilError):
         st.stencil_batch_describe(probs[0].coeffs, probs[0].spec.r, probs[0].interior, np.float64, -1)
+
+
+@pytest.mark.parametrize("ndim,kind,r", [(3, "box", 2), (3, "general", 2), (2, "general", 3), (2, "general", 4),
+                                         (3, "star", 3)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_depth_hint_without_a_blocked_kernel(ndim, kind, r, dtype):
+    # a variant with no blocked kernel for this dtype (compiled depth 0) takes
+    # the plain kernel whatever depth is hinted, with every scheme flag; a
+    # depth-0 candidate once reached the pass schedule and divided by zero
+    shape = (13, 70, 140) if ndim == 3 else (150, 1100)
+    w = wl.random_coeffs(ndim, "box" if kind == "general" else kind, r, 5).copy()
+    if kind == "general":
+        w[(0,) * ndim] = 0.0
+    for depth in (0, 1, 3, 99):
+        for flags in (0, st.STENCIL_FLAG_DEVICE_TILING, st.STENCIL_FLAG_OVERLAPPED_TILING):
+            info = _plan_w(w, r, shape, dtype, 50, depth=depth, flags=flags)
+            assert info["depth"] >= 1 and info["passes"] == -(-50 // info["depth"])
+            if info["scheme_name"] == "naive":
+                assert info["depth"] == 1
+
+
+def _plan_w(w, r, shape, dtype, T, **kw):
+    p = st.Plan(w, r, shape, dtype, T, flags=NC | kw.pop("flags", 0), **kw)
+    info = p.info
+    p.close()
+    return info
