@@ -542,7 +542,7 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
             kept[k] = res
     with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=SERVE_SLOTS) as srv:
         res = serving.serve_open_loop(srv, reqs, arr, on_result=keep)
-    # latency from each request's scheduled arrival (the driver's lag to the
+    # latency from each request's scheduled arrival (the open-loop client's lag to the
     # submit call included) to the end of the round that completes it
     alat = res["arrival_latency_s"]
     lat = np.array(alat[warmup:]) if len(alat) > warmup else np.array(alat)
@@ -587,7 +587,7 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
                       "served_gcells_per_s": round(ws["cell_updates"] / max(ws["wall_s"], 1e-9) / 1e9, 1),
                       "p50_ms": round(float(np.percentile(wl_, 50)) * 1e3, 2),
                       "p99_ms": round(float(np.percentile(wl_, 99)) * 1e3, 2),
-                      # the driver's lateness in submitting: the host staging of
+                      # the open-loop client's lateness in submitting: the host staging of
                       # the inputs bounds the load that reaches the server
                       "submit_lag_ms": round(float(wres["submit_lag_s"]) * 1e3, 1)})
         log(f"  serving sweep {sweep[-1]}")

@@ -129,7 +129,7 @@ struct stencil_server_s {
   hipStream_t compute = nullptr, copy = nullptr, collect = nullptr;
   // the server's own stream-ordered pool: request grids and round workspaces
   // come from it, and it keeps freed memory up to the budget instead of
-  // returning it to the driver at every synchronisation (the default pool's
+  // returning it to the runtime at every synchronisation (the default pool's
   // behaviour), so admissions reuse memory rather than map new pages while
   // the scheduler holds the lock
   hipMemPool_t pool = nullptr;
