@@ -113,15 +113,18 @@ __device__ __forceinline__ void run_2d(const BatchJob<Real>& J, int pass, int ti
     // so the level loop unrolls without per-level checks, as in the
     // single-grid kernel; the remainder pass takes it at run time. One tile
     // body serves interior and edge strips here (the fused kernel's register
-    // budget has no room for a second copy).
+    // budget has no room for a second copy). The level rings keep 2r slots:
+    // the work-list loop's state leaves no room for the wider ring (the
+    // 25-point box's kernel would double its AGPR use).
     if (SPLIT && d == DEPTH)
-      tb2d_tile<Real, R, SHAPE, DEPTH, V>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0, Y1, DEPTH);
+      tb2d_tile<Real, R, SHAPE, DEPTH, V, false>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb, Y0, Y1,
+                                                 DEPTH);
     else if (d == DEPTH)
-      tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb,
-                                                     Y0, Y1, DEPTH);
+      tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true, false>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la,
+                                                            lb, Y0, Y1, DEPTH);
     else
-      tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la, lb,
-                                                     Y0, Y1, d);
+      tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true, false>(wl, src, dst, in, P, Q, hq, lane, edge, X0, la,
+                                                            lb, Y0, Y1, d);
   }
 }
 

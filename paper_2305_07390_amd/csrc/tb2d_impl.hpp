@@ -129,11 +129,22 @@ __device__ __forceinline__ Tile2D locate_2d(int tile, int ns, int seg_len, int s
   return g;
 }
 
-template <int R>
-struct Ring0 {
-  // level-0 row slots: prefetch distance + 1, chosen so the rotation period
-  // lcm(2r, slots) stays short
-  static constexpr int value = !STENCIL_ABL_PREFETCH ? 1 : (2 * R >= 4) ? 2 * R : 4;
+// Register rings of a tile: `slots` partial-sum rows per level and `z0`
+// level-0 rows in flight (prefetch distance + 1), both rotated at compile time
+// over an unroll of lcm(slots, z0) rows.
+//
+// With 2r slots the output a row completes and the output it opens share a
+// slot: both are live at once, so unless the unroll lets the allocator rotate
+// 2r + 1 registers, every level copies the completed row. Radius-2 boxes
+// (the 25-point box: the most FMAs per row) take 2r + 1 slots and five rows
+// in flight, an unroll of five that rotates both rings (measured on 8192^2
+// FP64: +3 % at depths 5 and 6). WIDE = false keeps 2r slots (the fused batch
+// kernels, whose one register allocation has no room for the extra row).
+template <int R, int SHAPE, bool WIDE>
+struct LevelRing {
+  static constexpr bool wide = WIDE && R == 2 && SHAPE == kBox;
+  static constexpr int slots = wide ? 2 * R + 1 : 2 * R;
+  static constexpr int z0 = !STENCIL_ABL_PREFETCH ? 1 : wide ? 5 : (2 * R >= 4) ? 2 * R : 4;
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -222,11 +233,10 @@ __device__ __forceinline__ void extend_row_open(const Real (&x)[V], Real (&xe)[V
 }
 
 // Mutable per-tile streaming state (kept in registers after inlining).
-template <typename Real, int R, int DEPTH, int V>
+template <typename Real, int DEPTH, int V, int NS, int Z0>
 struct Tb2dState {
-  static constexpr int Z0 = Ring0<R>::value;
-  Real L0[Z0][V];          // level-0 rows in flight (prefetch ring)
-  Real A[DEPTH][2 * R][V]; // per level: partial sums of the 2r open output rows
+  Real L0[Z0][V];       // level-0 rows in flight (prefetch ring)
+  Real A[DEPTH][NS][V]; // per level: partial sums of the open output rows
 };
 
 // Per-tile constants.
@@ -241,13 +251,10 @@ struct Tb2dTile {
 // One streamed row (iteration i, phase ph of the unrolled loop).
 // GENERAL: warm-up/drain rows -- checks which levels hold valid rows and
 // handles the Dirichlet halo rows. Steady rows skip every check.
-template <typename Real, int R, int SHAPE, int DEPTH, int V, bool EDGE, bool GENERAL>
-__device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const Tb2dTile& t,
+template <typename Real, int R, int SHAPE, int DEPTH, int V, int NS, int Z0, bool EDGE, bool GENERAL>
+__device__ __forceinline__ void tb2d_row(Tb2dState<Real, DEPTH, V, NS, Z0>& st, const Tb2dTile& t,
                                          const Real* __restrict__ w, const Real* hq, const int ph,
                                          const int i) {
-  constexpr int R2 = 2 * R;
-  constexpr int Z0 = Ring0<R>::value;
-  constexpr int S = sizeof(Real);
   {
     const int ip = i + Z0 - 1;
     if (!GENERAL || ip < t.n_iter)
@@ -285,11 +292,12 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
     }
 
     // 1) the output completed by this arrival (dy = +r); it was started 2r
-    //    arrivals ago in the same slot
+    //    arrivals ago in the same slot (an output keeps the slot it opened in:
+    //    phase minus dy + r, modulo the slot count)
     Real out[V];
     {
       const int o = u - R;
-      const int sl = ph % R2;
+      const int sl = pmod(ph - 2 * R, NS);
       const bool halo_row = GENERAL && ((o < R) || (o >= Q - R));
       if (ok && !halo_row) add_row<Real, R, SHAPE, V>(st.A[s - 1][sl], x, xe, w, R);
 #pragma unroll
@@ -300,7 +308,7 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
 #pragma unroll
       for (int dy = R - 1; dy >= -R; --dy) {
         const int o = u - dy;
-        const int sl = pmod(ph - dy - R, R2);
+        const int sl = pmod(ph - dy - R, NS);
         const bool halo_row = GENERAL && ((o < R) || (o >= Q - R));
         if (halo_row) {
           if (dy == 0) {
@@ -329,15 +337,16 @@ __device__ __forceinline__ void tb2d_row(Tb2dState<Real, R, DEPTH, V>& st, const
 
 // One wave tile of one pass: d (<= DEPTH) levels from src to dst. EDGE: the
 // strip touches the left or right side of the grid (edge != kInterior).
-template <typename Real, int R, int SHAPE, int DEPTH, int V, bool EDGE>
+template <typename Real, int R, int SHAPE, int DEPTH, int V, bool EDGE, bool WIDE = true>
 __device__ __forceinline__ void tb2d_tile_impl(const Real* __restrict__ w, const void* src, void* dst,
                                           const void* orig, const int P, const int Q, Real* hq,
                                           const int lane, const int edge, const int X0,
                                           const int la, const int lb, const int Y0, const int Y1,
                                           const int d) {
-  constexpr int R2 = 2 * R;
-  constexpr int Z0 = Ring0<R>::value;
-  constexpr int UNROLL = lcm_c(R2, Z0);
+  using Ring = LevelRing<R, SHAPE, WIDE>;
+  constexpr int NS = Ring::slots;
+  constexpr int Z0 = Ring::z0;
+  constexpr int UNROLL = lcm_c(NS, Z0);
   constexpr int S = sizeof(Real);
 
   Tb2dTile t;
@@ -381,7 +390,7 @@ __device__ __forceinline__ void tb2d_tile_impl(const Real* __restrict__ w, const
     }
   }
 
-  Tb2dState<Real, R, DEPTH, V> st;
+  Tb2dState<Real, DEPTH, V, NS, Z0> st;
 #pragma unroll
   for (int z = 0; z < Z0; ++z)
 #pragma unroll
@@ -389,7 +398,7 @@ __device__ __forceinline__ void tb2d_tile_impl(const Real* __restrict__ w, const
 #pragma unroll
   for (int s = 0; s < DEPTH; ++s)
 #pragma unroll
-    for (int j = 0; j < R2; ++j)
+    for (int j = 0; j < NS; ++j)
 #pragma unroll
       for (int v = 0; v < V; ++v) st.A[s][j][v] = Real(0);
 
@@ -415,31 +424,31 @@ __device__ __forceinline__ void tb2d_tile_impl(const Real* __restrict__ w, const
   for (; base < i_a; base += UNROLL) {
 #pragma unroll
     for (int ph = 0; ph < UNROLL; ++ph)
-      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, EDGE, true>(st, t, w, hq, ph, base + ph);
+      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, NS, Z0, EDGE, true>(st, t, w, hq, ph, base + ph);
   }
   for (; base < i_b; base += UNROLL) {
 #pragma unroll
-    for (int ph = 0; ph < UNROLL; ++ph) tb2d_row<Real, R, SHAPE, DEPTH, V, EDGE, false>(st, t, w, hq, ph, base + ph);
+    for (int ph = 0; ph < UNROLL; ++ph) tb2d_row<Real, R, SHAPE, DEPTH, V, NS, Z0, EDGE, false>(st, t, w, hq, ph, base + ph);
   }
   for (; base < t.n_iter; base += UNROLL) {
 #pragma unroll
     for (int ph = 0; ph < UNROLL; ++ph)
-      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, EDGE, true>(st, t, w, hq, ph, base + ph);
+      if (base + ph < t.n_iter) tb2d_row<Real, R, SHAPE, DEPTH, V, NS, Z0, EDGE, true>(st, t, w, hq, ph, base + ph);
   }
 }
 
-template <typename Real, int R, int SHAPE, int DEPTH, int V>
+template <typename Real, int R, int SHAPE, int DEPTH, int V, bool WIDE = true>
 __device__ __forceinline__ void tb2d_tile(const Real* __restrict__ w, const void* src, void* dst,
                                           const void* orig, const int P, const int Q, Real* hq,
                                           const int lane, const int edge, const int X0,
                                           const int la, const int lb, const int Y0, const int Y1,
                                           const int d) {
   if (edge == kInterior && STENCIL_ABL_SPLIT_BODY)
-    tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, false>(w, src, dst, orig, P, Q, hq, lane, edge, X0, la,
-                                                    lb, Y0, Y1, d);
+    tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, false, WIDE>(w, src, dst, orig, P, Q, hq, lane, edge, X0,
+                                                          la, lb, Y0, Y1, d);
   else
-    tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true>(w, src, dst, orig, P, Q, hq, lane, edge, X0, la,
-                                                   lb, Y0, Y1, d);
+    tb2d_tile_impl<Real, R, SHAPE, DEPTH, V, true, WIDE>(w, src, dst, orig, P, Q, hq, lane, edge, X0,
+                                                         la, lb, Y0, Y1, d);
 }
 
 template <typename Real, int R, int SHAPE, int DEPTH>
