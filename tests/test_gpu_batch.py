@@ -126,3 +126,31 @@ def test_batch_mixes_alone_jobs(dtype):
     for p, f, y in zip(probs, fields, ys):
         ref = oracle.sweep(p.coeffs, p.spec.r, f, p.T)
         assert np.array_equal(y.cpu().numpy(), ref), (p.spec.name, p.interior, p.T)
+
+
+def test_batch_three_groups_side_by_side():
+    """One submission with FP32 jobs, fused FP64 jobs and FP64 3D radius-2
+    stars: three persistent launches (FP32 fused, FP64 fused, FP64 auxiliary)
+    one after another on the caller's stream. Every job equals the oracle,
+    twice in a row."""
+    import torch
+    cases = [
+        (wl.StencilSpec("2d_star_r1", 2, "star", 1), (300, 520), 17, np.float32),
+        (wl.StencilSpec("3d_star_r1", 3, "star", 1), (24, 70, 90), 5, np.float32),
+        (wl.StencilSpec("2d_box_r2", 2, "box", 2), (260, 640), 9, np.float64),
+        (wl.StencilSpec("3d_box_r1", 3, "box", 1), (20, 66, 80), 4, np.float64),
+        (wl.StencilSpec("3d_star_r2", 3, "star", 2), (30, 64, 100), 6, np.float64),
+        (wl.StencilSpec("3d_star_r2", 3, "star", 2), (14, 72, 64), 3, np.float64),
+    ]
+    probs = [wl.Problem(s, wl.coeffs_for(s, 500 + g), shp, T, field_seed=510 + g, tag=g)
+             for g, (s, shp, T, _) in enumerate(cases)]
+    fields = [p.field(dt) for p, (_, _, _, dt) in zip(probs, cases)]
+    refs = [oracle.sweep(p.coeffs, p.spec.r, f, p.T) for p, f in zip(probs, fields)]
+    xs = [torch.from_numpy(f).cuda() for f in fields]
+    for _ in range(2):
+        ys = [torch.full_like(x, float("nan")) for x in xs]
+        status = st.run_batch(probs, xs, ys)
+        assert all(s == st.STENCIL_OK for s in status), status
+        st.stencil_sync(torch.cuda.current_stream().cuda_stream)
+        for p, y, ref in zip(probs, ys, refs):
+            assert np.array_equal(y.cpu().numpy(), ref), (p.spec.name, p.interior, p.T)
