@@ -20,8 +20,9 @@ in one persistent launch per dtype (FP64 and FP32, with the FP32 error against
 the FP64 result and the fraction of its bytes/flops bound) and the serving
 loop under Poisson arrivals (FP32, 200 warm-up + measured requests, p50/p99
 latency from each request's scheduled arrival, an FP32 error sample, FP64
-plain throughput, a saturation sweep (400-1600 req/s) that gives the served
-capacity, and a small-budget stress run). The 3D rows carry device tiling's
+plain throughput, the same arrivals with two rounds in flight, a saturation
+sweep (400-1600 req/s) that gives the served capacity, and a small-budget
+stress run). The 3D rows carry device tiling's
 best measured rate next to the overlapped tiles the planner picks.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--T 1000]
@@ -572,6 +573,19 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
         t64 += timed(torch, lambda: plan.execute(x, y))
         u64 += prob.cells * T
         plan.close()
+    # the same arrivals with two rounds in flight (the next round enqueued
+    # shortly before the running one ends): latency under this load
+    with serving.Server(hbm_budget_bytes=200 * 10**9, max_slots=SERVE_SLOTS, rounds_in_flight=2) as srv:
+        res2 = serving.serve_open_loop(srv, reqs, arr)
+    a2 = res2["arrival_latency_s"]
+    lat2 = np.array(a2[warmup:]) if len(a2) > warmup else np.array(a2)
+    s2 = res2["stats"]
+    two_rounds = {"completed": s2["completed"], "rounds": s2["rounds"],
+                  "throughput_gcells_per_s": round(s2["cell_updates"] / max(s2["wall_s"], 1e-9) / 1e9, 1),
+                  "p50_ms": round(float(np.percentile(lat2, 50)) * 1e3, 2),
+                  "p99_ms": round(float(np.percentile(lat2, 99)) * 1e3, 2),
+                  "mean_ms": round(float(lat2.mean()) * 1e3, 2)}
+    log(f"  serving, two rounds in flight: {two_rounds}")
     # saturation sweep: offered load past the served capacity; the served
     # throughput plateaus at the capacity while p99 grows with the queue
     sweep = []
@@ -615,6 +629,7 @@ def bench_serving(np, torch, stencil, workloads, seconds=10.0, rate=200.0, warmu
            "submit_lag_ms": round(float(res["submit_lag_s"]) * 1e3, 2),
            "f32_max_err_rel_to_max": err, "f32_err_sample": len(kept),
            "fp64_plain_gcells_per_s_first200": round(u64 / max(t64, 1e-9) / 1e9, 1),
+           "two_rounds_in_flight": two_rounds,
            "saturation_sweep": sweep,
            "served_fp32_capacity_gcells_per_s": max(r["served_gcells_per_s"] for r in sweep),
            "stress": {"budget_GB": 0.5, "rate": 2 * rate, "requests": 400, "completed": ss["completed"],

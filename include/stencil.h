@@ -431,13 +431,19 @@ stencil_status stencil_tune_cache_clear(void);
  * scheduler thread. Requests (a stencil_job whose in/out are ignored, plus the
  * padded input grid in host memory, copied at submit so the caller may reuse
  * it) wait in a FIFO queue. Admission: a request enters when a slot is free
- * and the device memory it needs (two padded grids plus the batch workspace,
- * held until its result is collected) fits in the HBM budget; the input is
- * copied to the device on the copy stream while the current round runs. Each
- * round runs the next quantum (at most quantum_passes passes of the request's
- * temporal depth) of every resident request in one stencil_batch_submit, so a
- * request that arrives mid-round starts at the next round and its work shares
- * the device with the others'. A quantum is quantum_passes passes; with
+ * and the device memory it needs (two padded grids plus one batch workspace
+ * per round in flight, held until its result is collected) fits in the HBM
+ * budget; the input is copied to the device on the copy stream while rounds
+ * run. Each round runs the next quantum (at most quantum_passes passes of the
+ * request's temporal depth) of every resident request in one
+ * stencil_batch_submit, so a request that arrives mid-round starts at the
+ * next round composed after its admission and its work shares the device
+ * with the others'. With rounds_in_flight = 2 the next round is composed and
+ * enqueued shortly before the running one is expected to end, which hides
+ * the host's work between rounds (lower latency under moderate load) but
+ * makes rounds smaller under saturation (lower capacity); with 1 (the
+ * default) it is composed when the running one has ended. A quantum
+ * is quantum_passes passes; with
  * round_target_s > 0 it is at least the request's fair share of a round of
  * that duration (the throughput measured over past rounds, divided by the
  * resident requests and the request's cells, in whole passes). Latency is measured from submit to the end of
@@ -446,7 +452,8 @@ stencil_status stencil_tune_cache_clear(void);
  * (running T steps as several quanta is the same arithmetic).
  *
  * stencil_server_create: budget > 0, max_slots >= 1; quantum_passes <= 0
- *   means 4; round_target_s <= 0 turns the fair share off. Fails with
+ *   means 4; round_target_s <= 0 turns the fair share off; rounds_in_flight
+ *   <= 0 means 1, and above 2 is STENCIL_ERR_INVALID. Fails with
  *   STENCIL_ERR_DEVICE when the device is unusable.
  * stencil_server_submit: STENCIL_ERR_BUDGET if the request alone exceeds the
  *   budget, STENCIL_ERR_INVALID for a bad job (as stencil_plan) or NULL
@@ -459,8 +466,8 @@ stencil_status stencil_tune_cache_clear(void);
  *   until the request is done, then behaves like poll.
  * stencil_server_stats: counters and latency percentiles over the requests
  *   completed so far (nearest-rank p50 / p99).
- * stencil_server_destroy: stops the scheduler after the round in flight,
- *   drops pending requests and releases all device memory. */
+ * stencil_server_destroy: stops the scheduler, waits for the rounds in
+ *   flight, drops pending requests and releases all device memory. */
 typedef struct stencil_server_s* stencil_server_t;
 
 typedef struct {
@@ -469,6 +476,7 @@ typedef struct {
   int32_t quantum_passes;    /* passes per request per round (<= 0: 4) */
   uint64_t hbm_budget_bytes; /* device memory for resident requests */
   double round_target_s;     /* > 0: fair share of a round of this duration */
+  int32_t rounds_in_flight;  /* rounds enqueued at a time, 1 or 2 (<= 0: 1) */
 } stencil_server_config;
 
 typedef struct {

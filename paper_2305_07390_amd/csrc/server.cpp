@@ -2,10 +2,14 @@
 // budget and slots, stay resident on the device, and advance in rounds. Each
 // round runs one quantum of every resident request in one batched persistent
 // launch (stencil_batch_submit), so requests that arrive while others run are
-// batched with them from the next round on (continuous batching). A quantum is
-// a few passes of the request's temporal depth; running T steps as several
-// quanta is the same arithmetic as one run, so results do not depend on the
-// mix.
+// batched with them from a following round on (continuous batching). A
+// quantum is a few passes of the request's temporal depth; running T steps as
+// several quanta is the same arithmetic as one run, so results do not depend
+// on the mix. By default the next round is composed when the running one
+// has ended; with two rounds in flight it is composed and enqueued shortly
+// before the running one is expected to end, so the device does not wait on
+// the host between rounds (measured on MI355X: lower latency under moderate
+// load, but smaller rounds and lower capacity under saturation).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -105,21 +109,52 @@ struct Request {
   // the batched plan, made once at submit; each round runs a copy
   // rescheduled for its steps
   std::unique_ptr<stencil_plan_s> plan;
-  void* host_in = nullptr;  // pinned copy of the input (released after the first round)
+  void* host_in = nullptr;  // pinned copy of the input (released once uploaded)
   size_t host_cls = 0;
   size_t bytes = 0;  // one padded grid
   size_t need = 0;   // device bytes held while resident
-  int64_t remaining = 0;
+  int64_t remaining = 0;    // steps not yet completed
+  int64_t unscheduled = 0;  // steps not yet in an enqueued round
+  bool scheduled = false;   // in an enqueued round at least once (T = 0 runs once)
   int64_t depth = 1;    // steps per pass of the batched plan
   int64_t cells = 1;
   char* dev = nullptr;  // two padded grids
-  int cur = 0;          // which half holds the current state
+  int cur = 0;          // which half holds the state after the completed rounds
+  int cur_next = 0;     // which half the next enqueued round reads
   RState state = RState::kQueued;
   bool collecting = false;
   stencil_status err = STENCIL_OK;
   Clock::time_point t_submit, t_done;
   double updates = 0;
   void* grid(int k) const { return dev + (size_t)k * ((bytes + 255) / 256 * 256); }
+};
+
+// A round in flight: its requests and their steps, the event recorded after
+// its launches, and the pinned word that receives the compute stream's report
+// word (watchdog expiries) just before that event, so that a round's outcome
+// is known without waiting for the round enqueued after it.
+struct Round {
+  std::vector<Request*> reqs;
+  std::vector<int64_t> steps;
+  hipEvent_t done = nullptr;
+  unsigned int* report = nullptr;
+  double updates = 0;
+  Clock::time_point t0;
+  stencil_status st = STENCIL_OK;  // status of enqueueing it
+};
+
+constexpr int kMaxRoundsInFlight = 2;
+// With two rounds in flight the next round is composed this long before the
+// running one is expected to end (its cell-updates at the measured
+// throughput): late enough that the arrivals admitted meanwhile join it,
+// early enough to hide the host's work between rounds.
+constexpr double kComposeLead_s = 2e-3;
+
+// An admission's upload on the copy stream, marked by an event; the pinned
+// input block goes back to the pool as soon as the event completes.
+struct Upload {
+  hipEvent_t done = nullptr;
+  uint64_t ticket = 0;
 };
 
 }  // namespace
@@ -133,7 +168,11 @@ struct stencil_server_s {
   // behaviour), so admissions reuse memory rather than map new pages while
   // the scheduler holds the lock
   hipMemPool_t pool = nullptr;
-  hipEvent_t round_end = nullptr, inputs_ready = nullptr, copy_mark = nullptr;
+  hipEvent_t inputs_ready = nullptr, copy_mark = nullptr;
+  Round rounds[kMaxRoundsInFlight];
+  std::deque<int> inflight;  // indices into rounds, oldest first
+  std::deque<Upload> uploads;  // in copy-stream order
+  Clock::time_point last_round_end;
   std::mutex mu;
   std::condition_variable cv_work;  // new submissions or stop
   std::condition_variable cv_done;  // a request finished
@@ -180,6 +219,16 @@ void admit_locked(stencil_server_s* srv) {
     hipError_t e = hipMallocFromPoolAsync((void**)&r->dev, two, srv->pool, srv->copy);
     if (e == hipSuccess)
       e = hipMemcpyAsync(r->dev, r->host_in, r->bytes, hipMemcpyHostToDevice, srv->copy);
+    if (e == hipSuccess) {
+      // without an event the block is released when the request's first
+      // round completes instead
+      Upload u;
+      u.ticket = r->ticket;
+      if (hipEventCreateWithFlags(&u.done, hipEventDisableTiming) == hipSuccess) {
+        if (hipEventRecord(u.done, srv->copy) == hipSuccess) srv->uploads.push_back(u);
+        else (void)hipEventDestroy(u.done);
+      }
+    }
     if (e != hipSuccess) {
       if (r->dev) (void)hipFreeAsync(r->dev, srv->copy);
       r->dev = nullptr;
@@ -206,100 +255,208 @@ void admit_locked(stencil_server_s* srv) {
   srv->st.queued = (int32_t)srv->adm.queue.size();
 }
 
+// Gives the pinned input blocks of completed uploads back to the pool (the
+// copy stream runs them in order, so the first pending one ends the scan).
+// Called with the lock held.
+void reap_uploads_locked(stencil_server_s* srv) {
+  while (!srv->uploads.empty()) {
+    Upload& u = srv->uploads.front();
+    const hipError_t q = hipEventQuery(u.done);
+    if (q == hipErrorNotReady) break;
+    auto it = srv->all.find(u.ticket);
+    if (q == hipSuccess && it != srv->all.end() && it->second->host_in) {
+      Request* r = it->second.get();
+      srv->pinned.put(r->host_in, r->host_cls);
+      r->host_in = nullptr;
+    }
+    (void)hipEventDestroy(u.done);
+    srv->uploads.pop_front();
+  }
+}
+
+// Whether a resident request still has steps to put into a round.
+bool schedulable(const Request* r) {
+  return r->state == RState::kResident && (r->unscheduled > 0 || !r->scheduled);
+}
+
+// Composes the next round from the resident requests and enqueues it on the
+// compute stream into rounds[slot]. Called with the lock held; releases it
+// while enqueueing. Returns false when no request has steps left to schedule.
+bool enqueue_round(stencil_server_s* srv, std::unique_lock<std::mutex>& lock, int slot) {
+  Round& R = srv->rounds[slot];
+  R.reqs.clear();
+  R.steps.clear();
+  for (Request* r : srv->adm.resident)
+    if (schedulable(r)) R.reqs.push_back(r);
+  if (R.reqs.empty()) return false;
+  // one quantum of every request: its fair share of the round's work, in
+  // whole passes
+  const size_t n = R.reqs.size();
+  std::vector<const stencil_plan_s*> plans(n);
+  std::vector<const void*> ins(n);
+  std::vector<void*> outs(n);
+  const double share = srv->cfg.round_target_s > 0 ? srv->cfg.round_target_s * srv->rate / (double)n : 0.0;
+  R.updates = 0;
+  for (size_t k = 0; k < n; ++k) {
+    Request* r = R.reqs[k];
+    int64_t q = (int64_t)(share / (double)r->cells) / r->depth * r->depth;
+    q = std::max<int64_t>(q, (int64_t)srv->cfg.quantum_passes * r->depth);
+    const int64_t steps = std::min(r->unscheduled, q);
+    R.steps.push_back(steps);
+    R.updates += (double)steps * (double)r->cells;
+    plans[k] = r->plan.get();
+    ins[k] = r->grid(r->cur_next);
+    outs[k] = r->grid(1 - r->cur_next);
+    // the request's state as the rounds enqueued so far leave it
+    r->unscheduled -= steps;
+    r->cur_next = 1 - r->cur_next;
+    r->scheduled = true;
+  }
+  const bool wait_inputs = srv->pending_inputs;
+  srv->pending_inputs = false;
+  lock.unlock();
+  R.t0 = Clock::now();
+  stencil_status st = STENCIL_OK;
+  if (wait_inputs) {
+    // admissions copied since the last round: their inputs first
+    if (hipEventRecord(srv->inputs_ready, srv->copy) != hipSuccess ||
+        hipStreamWaitEvent(srv->compute, srv->inputs_ready, 0) != hipSuccess)
+      st = hip_fail(hipErrorUnknown, "server input ordering");
+  }
+  if (st == STENCIL_OK) st = batch_submit_planned(plans, R.steps, ins, outs, srv->compute, srv->pool);
+  if (st == STENCIL_OK) {
+    unsigned int* word = stream_report_word(srv->compute);
+    hipError_t e = word ? hipMemcpyAsync(R.report, word, sizeof(unsigned int), hipMemcpyDeviceToHost, srv->compute)
+                        : hipErrorOutOfMemory;
+    if (e == hipSuccess) e = hipEventRecord(R.done, srv->compute);
+    if (e != hipSuccess) st = hip_fail(e, "server round event");
+  }
+  R.st = st;
+  lock.lock();
+  srv->inflight.push_back(slot);
+  return true;
+}
+
+// Fails every request of every round in flight (after a failed enqueue or an
+// expired device wait) once the compute stream is idle, and clears the
+// stream's report word. Called with the lock held; releases it while waiting.
+void fail_inflight(stencil_server_s* srv, std::unique_lock<std::mutex>& lock, stencil_status st) {
+  lock.unlock();
+  (void)hipStreamSynchronize(srv->compute);
+  (void)stencil_sync(srv->compute);  // reads and clears the report word
+  lock.lock();
+  for (int slot : srv->inflight) {
+    Round& R = srv->rounds[slot];
+    srv->st.rounds++;
+    for (Request* r : R.reqs) {
+      if (r->host_in) {
+        srv->pinned.put(r->host_in, r->host_cls);
+        r->host_in = nullptr;
+      }
+      if (r->state == RState::kResident) finish_locked(srv, r, RState::kFailed, st);
+    }
+    R.reqs.clear();
+  }
+  srv->inflight.clear();
+  srv->cv_done.notify_all();
+}
+
+// Retires the oldest round, which has completed: its requests advance, and
+// those with no steps left are done. Called with the lock held.
+void retire_round(stencil_server_s* srv) {
+  const int slot = srv->inflight.front();
+  srv->inflight.pop_front();
+  Round& R = srv->rounds[slot];
+  const Clock::time_point now = Clock::now();
+  // busy time of this round: from its enqueue or the previous round's end,
+  // whichever is later (the rounds overlap in the queue, not on the device)
+  const Clock::time_point from = std::max(R.t0, srv->last_round_end);
+  const double busy = std::chrono::duration<double>(now - from).count();
+  srv->last_round_end = now;
+  srv->st.rounds++;
+  srv->st.busy_s += busy;
+  if (busy > 0) {
+    // throughput of this round, smoothed; small rounds under-fill the
+    // device, so only rounds near the target duration update it upward
+    const double r_now = R.updates / busy;
+    if (srv->cfg.round_target_s <= 0 || busy >= 0.5 * srv->cfg.round_target_s || r_now < srv->rate)
+      srv->rate = 0.7 * srv->rate + 0.3 * r_now;
+  }
+  for (size_t k = 0; k < R.reqs.size(); ++k) {
+    Request* r = R.reqs[k];
+    if (r->host_in) {  // its upload finished before its first round started
+      srv->pinned.put(r->host_in, r->host_cls);
+      r->host_in = nullptr;
+    }
+    r->cur = 1 - r->cur;
+    r->remaining -= R.steps[k];
+    if (r->remaining == 0 && r->unscheduled == 0) finish_locked(srv, r, RState::kDone, STENCIL_OK);
+  }
+  R.reqs.clear();
+  srv->cv_done.notify_all();
+}
+
+// Whether the next round should be composed now: no round is in flight, or
+// the oldest one is expected to end within the lead. Called with the lock held.
+bool compose_now(const stencil_server_s* srv) {
+  if (srv->inflight.empty()) return true;
+  if ((int)srv->inflight.size() >= srv->cfg.rounds_in_flight) return false;
+  const Round& R = srv->rounds[srv->inflight.front()];
+  const Clock::time_point start = std::max(R.t0, srv->last_round_end);
+  const double expected = R.updates / std::max(srv->rate, 1e9) - kComposeLead_s;
+  return std::chrono::duration<double>(Clock::now() - start).count() >= expected;
+}
+
 void scheduler(stencil_server_s* srv) {
   (void)hipSetDevice(srv->cfg.device);
   std::unique_lock<std::mutex> lock(srv->mu);
-  while (true) {
-    if (srv->stop) break;
+  while (!srv->stop) {
     admit_locked(srv);
-    std::vector<Request*> round;
-    for (Request* r : srv->adm.resident)
-      if (r->state == RState::kResident) round.push_back(r);
-    if (round.empty()) {
-      if (srv->stop) break;
+    reap_uploads_locked(srv);
+    // the next round, enqueued behind the running one near its end
+    if (compose_now(srv)) {
+      int slot = 0;
+      while (slot < kMaxRoundsInFlight &&
+             std::find(srv->inflight.begin(), srv->inflight.end(), slot) != srv->inflight.end())
+        ++slot;
+      if (enqueue_round(srv, lock, slot)) {
+        if (srv->rounds[slot].st != STENCIL_OK) fail_inflight(srv, lock, srv->rounds[slot].st);
+        continue;
+      }
+    }
+    if (srv->inflight.empty()) {
       // sleep until a queued request fits (a submission, or a collection
       // that frees a slot and memory)
       srv->adm.wait_admissible(srv->cv_work, lock, [&] { return srv->stop; });
-      if (srv->stop) break;
       continue;
     }
-    // one quantum of every resident request, in one batched launch: each
-    // request's fair share of the round's work, in whole passes
-    std::vector<const stencil_plan_s*> plans(round.size());
-    std::vector<const void*> ins(round.size());
-    std::vector<void*> outs(round.size());
-    std::vector<int64_t> steps(round.size());
-    const double share = srv->cfg.round_target_s > 0
-                             ? srv->cfg.round_target_s * srv->rate / (double)round.size()
-                             : 0.0;
-    double round_updates = 0;
-    for (size_t k = 0; k < round.size(); ++k) {
-      Request* r = round[k];
-      int64_t q = (int64_t)(share / (double)r->cells) / r->depth * r->depth;
-      q = std::max<int64_t>(q, (int64_t)srv->cfg.quantum_passes * r->depth);
-      steps[k] = std::min(r->remaining, q);
-      round_updates += (double)steps[k] * (double)r->cells;
-      plans[k] = r->plan.get();
-      ins[k] = r->grid(r->cur);
-      outs[k] = r->grid(1 - r->cur);
-    }
-    const bool wait_inputs = srv->pending_inputs;
-    srv->pending_inputs = false;
-    lock.unlock();
+    // wait for the oldest round; meanwhile admit arrivals, and go back to
+    // enqueue the next one once the oldest is near its end and there is work
+    Round& R = srv->rounds[srv->inflight.front()];
     stencil_status st = STENCIL_OK;
-    if (wait_inputs) {
-      if (hipEventRecord(srv->inputs_ready, srv->copy) != hipSuccess ||
-          hipStreamWaitEvent(srv->compute, srv->inputs_ready, 0) != hipSuccess)
-        st = hip_fail(hipErrorUnknown, "server input ordering");
-    }
-    const Clock::time_point t0 = Clock::now();
-    if (st == STENCIL_OK) st = batch_submit_planned(plans, steps, ins, outs, srv->compute, srv->pool);
-    if (st == STENCIL_OK && hipEventRecord(srv->round_end, srv->compute) != hipSuccess)
-      st = hip_fail(hipErrorUnknown, "server round event");
-    // while the round runs, admit arrivals so their inputs are on the device
-    // by the next round
-    lock.lock();
-    while (st == STENCIL_OK) {
-      const hipError_t q = hipEventQuery(srv->round_end);
-      if (q == hipSuccess) break;
+    bool completed = false;
+    while (!srv->stop) {
+      const hipError_t q = hipEventQuery(R.done);
+      if (q == hipSuccess) {
+        completed = true;
+        break;
+      }
       if (q != hipErrorNotReady) {
         st = hip_fail(q, "server round");
         break;
       }
       admit_locked(srv);
+      reap_uploads_locked(srv);
+      if (compose_now(srv) && std::any_of(srv->adm.resident.begin(), srv->adm.resident.end(), schedulable))
+        break;
       srv->cv_work.wait_for(lock, std::chrono::microseconds(100));
     }
-    lock.unlock();
-    if (st == STENCIL_OK) st = stencil_sync(srv->compute);
-    // a failed round may have left work queued: nothing of this round's
-    // requests is released before the compute stream is idle
-    if (st != STENCIL_OK) (void)hipStreamSynchronize(srv->compute);
-    const double busy = std::chrono::duration<double>(Clock::now() - t0).count();
-    lock.lock();
-    srv->st.rounds++;
-    srv->st.busy_s += busy;
-    if (st == STENCIL_OK && busy > 0) {
-      // throughput of this round, smoothed; small rounds under-fill the
-      // device, so only rounds near the target duration update it upward
-      const double r_now = round_updates / busy;
-      if (srv->cfg.round_target_s <= 0 || busy >= 0.5 * srv->cfg.round_target_s || r_now < srv->rate)
-        srv->rate = 0.7 * srv->rate + 0.3 * r_now;
+    if (st == STENCIL_OK && completed && *R.report != 0u) st = STENCIL_ERR_TIMEOUT;
+    if (st != STENCIL_OK) {
+      fail_inflight(srv, lock, st);
+      continue;
     }
-    for (size_t k = 0; k < round.size(); ++k) {
-      Request* r = round[k];
-      if (r->host_in) {  // its input copy finished before this round started
-        srv->pinned.put(r->host_in, r->host_cls);
-        r->host_in = nullptr;
-      }
-      if (st != STENCIL_OK) {
-        finish_locked(srv, r, RState::kFailed, st);
-        continue;
-      }
-      r->cur = 1 - r->cur;
-      r->remaining -= steps[k];
-      if (r->remaining == 0) finish_locked(srv, r, RState::kDone, STENCIL_OK);
-    }
-    srv->cv_done.notify_all();
+    if (completed) retire_round(srv);
   }
 }
 
@@ -378,6 +535,8 @@ stencil_status stencil_server_create(const stencil_server_config* config, stenci
   *server = nullptr;
   if (config->max_slots < 1) return fail(STENCIL_ERR_INVALID, "max_slots must be >= 1");
   if (config->hbm_budget_bytes == 0) return fail(STENCIL_ERR_INVALID, "HBM budget must be > 0");
+  if (config->rounds_in_flight > kMaxRoundsInFlight)
+    return fail(STENCIL_ERR_INVALID, "rounds_in_flight must be 1 or 2");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || config->device < 0 || config->device >= ndev)
     return fail(STENCIL_ERR_DEVICE, "HIP device %d is not available", config->device);
@@ -386,6 +545,7 @@ stencil_status stencil_server_create(const stencil_server_config* config, stenci
   srv->cfg = *config;
   srv->adm.budget = config->hbm_budget_bytes;
   srv->adm.slots = config->max_slots;
+  if (srv->cfg.rounds_in_flight <= 0) srv->cfg.rounds_in_flight = 1;
   if (srv->cfg.quantum_passes <= 0) srv->cfg.quantum_passes = 4;
   if (!(srv->cfg.round_target_s > 0)) srv->cfg.round_target_s = 0.0;
   std::memset(&srv->st, 0, sizeof(srv->st));
@@ -395,7 +555,11 @@ stencil_status stencil_server_create(const stencil_server_config* config, stenci
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->compute, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->copy, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->collect, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->round_end, hipEventDisableTiming);
+  for (int k = 0; k < kMaxRoundsInFlight && e == hipSuccess; ++k) {
+    e = hipEventCreateWithFlags(&srv->rounds[k].done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&srv->rounds[k].report, sizeof(unsigned int), hipHostMallocDefault);
+    if (e == hipSuccess) *srv->rounds[k].report = 0u;
+  }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->inputs_ready, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->copy_mark, hipEventDisableTiming);
   if (e == hipSuccess) {
@@ -440,9 +604,10 @@ stencil_status stencil_server_submit(stencil_server_t srv, const stencil_job* jo
     return fail(STENCIL_ERR_NOMEM, "host allocation failed");
   }
   r->bytes = (size_t)pl->padded_elems * pl->elem;
-  // two resident grids plus the batch workspace of a round
-  r->need = 2 * align256(r->bytes) + align256(r->bytes);
+  // two resident grids plus the batch workspaces of the rounds in flight
+  r->need = (2 + (size_t)srv->cfg.rounds_in_flight) * align256(r->bytes);
   r->remaining = job->T;
+  r->unscheduled = job->T;
   r->updates = (double)pl->cells * (double)job->T;
   r->depth = pl->scheme == STENCIL_SCHEME_NAIVE ? 1 : std::max(1, pl->depth);
   r->cells = std::max<int64_t>(1, pl->cells);
@@ -520,13 +685,18 @@ stencil_status stencil_server_destroy(stencil_server_t srv) {
   (void)hipSetDevice(srv->cfg.device);
   if (srv->compute) (void)hipStreamSynchronize(srv->compute);
   if (srv->copy) (void)hipStreamSynchronize(srv->copy);
+  for (Upload& u : srv->uploads) (void)hipEventDestroy(u.done);
+  srv->uploads.clear();
   for (auto& kv : srv->all) {
     if (kv.second->dev) (void)hipFreeAsync(kv.second->dev, srv->collect);
     srv->pinned.put(kv.second->host_in, kv.second->host_cls);  // freed with the pool
     kv.second->host_in = nullptr;
   }
   if (srv->collect) (void)hipStreamSynchronize(srv->collect);
-  if (srv->round_end) (void)hipEventDestroy(srv->round_end);
+  for (int k = 0; k < kMaxRoundsInFlight; ++k) {
+    if (srv->rounds[k].done) (void)hipEventDestroy(srv->rounds[k].done);
+    if (srv->rounds[k].report) (void)hipHostFree(srv->rounds[k].report);
+  }
   if (srv->inputs_ready) (void)hipEventDestroy(srv->inputs_ready);
   if (srv->copy_mark) (void)hipEventDestroy(srv->copy_mark);
   if (srv->compute) (void)hipStreamDestroy(srv->compute);

@@ -18,9 +18,9 @@ class Server:
     """Context-managed native server on one device."""
 
     def __init__(self, hbm_budget_bytes: int, max_slots: int, quantum_passes: int = 0, device: int = 0,
-                 round_target_s: float = 0.0):
+                 round_target_s: float = 0.0, rounds_in_flight: int = 0):
         self.handle = st.stencil_server_create(hbm_budget_bytes, max_slots, quantum_passes, device,
-                                               round_target_s)
+                                               round_target_s, rounds_in_flight)
 
     def submit(self, coeffs, radius: int, interior, T: int, field: np.ndarray) -> int:
         return st.stencil_server_submit(self.handle, coeffs, radius, interior, T, field)

@@ -128,7 +128,7 @@ class stencil_tune_result(ctypes.Structure):
 class stencil_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("quantum_passes", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_uint64),
-                ("round_target_s", ctypes.c_double)]
+                ("round_target_s", ctypes.c_double), ("rounds_in_flight", ctypes.c_int32)]
 
 
 class stencil_server_statistics(ctypes.Structure):
@@ -478,9 +478,10 @@ def use_tuned_defaults(path: str = TUNE_CACHE_PATH) -> int:
 
 
 def stencil_server_create(hbm_budget_bytes: int, max_slots: int, quantum_passes: int = 0,
-                          device: int = 0, round_target_s: float = 0.0):
+                          device: int = 0, round_target_s: float = 0.0, rounds_in_flight: int = 0):
     cfg = stencil_server_config()
     cfg.round_target_s = float(round_target_s)
+    cfg.rounds_in_flight = int(rounds_in_flight)
     cfg.device = int(device)
     cfg.max_slots = int(max_slots)
     cfg.quantum_passes = int(quantum_passes)

@@ -31,12 +31,15 @@ def _small_requests(n, seed, dtype):
     return reqs, arr
 
 
+@pytest.mark.parametrize("rounds", [1, 2], ids=["one_round", "two_rounds"])
 @pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
-def test_served_results_equal_alone(dtype):
+def test_served_results_equal_alone(dtype, rounds):
     reqs, arr = _small_requests(24, seed=21, dtype=dtype)
     # one pass per request per round, so requests take several rounds and
-    # overlap with later arrivals
-    with serving.Server(hbm_budget_bytes=8 << 30, max_slots=16, quantum_passes=1) as srv:
+    # overlap with later arrivals (with two rounds in flight, also with the
+    # round enqueued behind theirs)
+    with serving.Server(hbm_budget_bytes=8 << 30, max_slots=16, quantum_passes=1,
+                        rounds_in_flight=rounds) as srv:
         out = serving.serve_open_loop(srv, reqs, arr, keep_results=True)
     assert not out["rejected"]
     s = out["stats"]
@@ -67,14 +70,17 @@ def test_burst_with_T0_and_naive_shapes():
             srv.wait(tickets[0])  # collected tickets are forgotten
 
 
-def test_admission_respects_budget_and_slots():
+@pytest.mark.parametrize("rounds", [1, 2], ids=["one_round", "two_rounds"])
+def test_admission_respects_budget_and_slots(rounds):
     spec = wl.SUITE_2D[0]
     coeffs = wl.coeffs_for(spec, 9)
     shape = (1024, 1024)
     grid_bytes = (1024 + 2) ** 2 * 8
-    need = 3 * ((grid_bytes + 255) // 256 * 256)
+    # two resident grids plus one batch workspace per round in flight
+    need = (2 + rounds) * ((grid_bytes + 255) // 256 * 256)
     budget = 2 * need + need // 2  # room for two resident requests
-    with serving.Server(hbm_budget_bytes=budget, max_slots=8, quantum_passes=1) as srv:
+    with serving.Server(hbm_budget_bytes=budget, max_slots=8, quantum_passes=1,
+                        rounds_in_flight=rounds) as srv:
         with pytest.raises(st.StencilError) as e:
             srv.submit(coeffs, spec.r, (2048, 2048), 10, wl.make_field((2048, 2048), 1, 1))
         assert e.value.status == st.STENCIL_ERR_BUDGET

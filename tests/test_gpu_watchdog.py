@@ -62,3 +62,31 @@ def test_batch_expiry_is_reported_then_clean(zero_watchdog):
     st.stencil_sync(st._stream_handle(None))
     for p, x, y in zip(probs, xs, ys):
         np.testing.assert_array_equal(y.cpu().numpy(), oracle.sweep(p.coeffs, p.spec.r, p.field(), p.T))
+
+
+@pytest.mark.parametrize("rounds", [1, 2], ids=["one_round", "two_rounds"])
+def test_server_round_expiry_fails_its_request_then_clean(zero_watchdog, rounds):
+    """A served request whose round's waits expire fails with
+    STENCIL_ERR_TIMEOUT (the round's report word is read when the round is
+    retired); the server clears the stream's report word, and the next
+    request, run with the default limit, equals the oracle."""
+    from paper_2305_07390_amd import serving
+    spec = wl.SUITE_2D[0]
+    coeffs = wl.coeffs_for(spec, 6)
+    u0 = wl.make_field((1024, 1024), 1, 6)
+    with serving.Server(hbm_budget_bytes=1 << 30, max_slots=4, quantum_passes=4,
+                        rounds_in_flight=rounds) as srv:
+        # three passes in one round: idle workgroups claim pass-1 items at
+        # once and find pass 0 unfinished
+        t = srv.submit(coeffs, 1, (1024, 1024), 36, u0)
+        print("server request T=36 at 1024^2, zero watchdog", flush=True)
+        with pytest.raises(st.StencilError) as e:
+            srv.wait(t, np.empty_like(u0))
+        assert e.value.status == st.STENCIL_ERR_TIMEOUT
+        os.environ.pop("STENCIL_WATCHDOG_US")
+        t = srv.submit(coeffs, 1, (1024, 1024), 36, u0)
+        got = np.empty_like(u0)
+        srv.wait(t, got)
+        s = srv.stats()
+    np.testing.assert_array_equal(got, oracle.sweep(coeffs, 1, u0, 36))
+    assert s["failed"] == 1 and s["completed"] == 1

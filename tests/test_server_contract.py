@@ -5,10 +5,10 @@ import pytest
 from paper_2305_07390_amd import stencil as st
 
 
-@pytest.mark.parametrize("budget,slots", [(0, 4), (1 << 30, 0)])
-def test_create_rejects_bad_config(budget, slots):
+@pytest.mark.parametrize("budget,slots,rounds", [(0, 4, 0), (1 << 30, 0, 0), (1 << 30, 4, 3)])
+def test_create_rejects_bad_config(budget, slots, rounds):
     with pytest.raises(st.StencilError) as e:
-        st.stencil_server_create(budget, slots)
+        st.stencil_server_create(budget, slots, rounds_in_flight=rounds)
     assert e.value.status == st.STENCIL_ERR_INVALID
 
 
