@@ -101,6 +101,9 @@ struct Buffers {
   }
 };
 
+// Timed runs per candidate (after one untimed run); the best one counts.
+constexpr int kTuneReps = 3;
+
 // Time `fn` (enqueues on s) once untimed, then `reps` times; best seconds.
 template <typename F>
 stencil_status time_best(hipStream_t s, int reps, F&& fn, double* best) {
@@ -273,9 +276,11 @@ stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_
   Candidate best = keep.front();
   int measured = 0;
   for (const Candidate& c : keep) {
-    // enough passes to time several milliseconds of work, at least four
+    // enough passes to time about ten milliseconds of work, at least four:
+    // neighbouring depths of one stencil can differ by 1-2 %, so a timing
+    // needs less noise than that
     const int64_t per_pass = cells * c.depth * replicas;
-    int64_t passes = std::max<int64_t>(4, (int64_t)(4.0e9 / (double)std::max<int64_t>(per_pass, 1)));
+    int64_t passes = std::max<int64_t>(4, (int64_t)(8.0e9 / (double)std::max<int64_t>(per_pass, 1)));
     passes = std::min<int64_t>(passes, 64);
     const int64_t Tp = passes * c.depth;
     double t = INFINITY;
@@ -288,7 +293,7 @@ stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_
       stencil_plan_t p = nullptr;
       st = stencil_plan(&p, coeffs, radius, shape, dtype, Tp, &h);
       if (st != STENCIL_OK) return st;
-      st = time_best(s, 2, [&] { return stencil_execute(p, in, outs[0], ws, s); }, &t);
+      st = time_best(s, kTuneReps, [&] { return stencil_execute(p, in, outs[0], ws, s); }, &t);
       stencil_plan_destroy(p);
     } else {
       std::vector<stencil_job> jobs(replicas);
@@ -305,7 +310,7 @@ stencil_status stencil_tune(const double* coeffs, int32_t radius, const stencil_
         j.tag = (uint64_t)i;
         j.depth = c.depth;
       }
-      st = time_best(s, 2, [&] { return stencil_batch_submit(jobs.data(), replicas, s, nullptr); }, &t);
+      st = time_best(s, kTuneReps, [&] { return stencil_batch_submit(jobs.data(), replicas, s, nullptr); }, &t);
     }
     if (st != STENCIL_OK) return st;
     ++measured;
