@@ -44,12 +44,10 @@ __device__ __forceinline__ T* uni_ptr(T* p) {
 // persistent item loop around it uniform too (a loop it believed divergent
 // was restructured into a lane-masked one).
 struct DeviceWait {
-  __device__ static unsigned load_acquire(const unsigned* p) {
-    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-  }
   __device__ static unsigned load_relaxed(const unsigned* p) {
     return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
   }
+  __device__ static void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
   __device__ static void raise(unsigned* p) {
     __hip_atomic_store(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }

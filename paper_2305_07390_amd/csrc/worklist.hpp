@@ -89,17 +89,22 @@ __host__ __device__ inline int find_chunk(const int64_t* first, int nchunks, int
 }
 
 // Waits until *ctr >= need. Returns false if the watchdog expired here (then
-// sets *err) or an earlier wait of the launch already failed. P supplies the
-// memory operations and the clock:
-//   unsigned load_acquire(const unsigned*), unsigned load_relaxed(const
-//   unsigned*), void raise(unsigned*) (store 1, relaxed), uint64_t now(),
-//   void pause().
+// sets *err) or an earlier wait of the launch already failed. The counter is
+// polled with relaxed loads and one acquire fence follows the load that sees
+// it reach `need` (on the device an acquire load at agent scope invalidates
+// cache lines at every poll, under the workgroups still streaming). P
+// supplies the memory operations and the clock:
+//   unsigned load_relaxed(const unsigned*), void acquire_fence(),
+//   void raise(unsigned*) (store 1, relaxed), uint64_t now(), void pause().
 template <class P>
 __host__ __device__ inline bool wait_count(const unsigned* ctr, unsigned need, unsigned* err,
                                            int64_t timeout_ticks) {
   const uint64_t t0 = P::now();
   while (true) {
-    if (P::load_acquire(ctr) >= need) return true;
+    if (P::load_relaxed(ctr) >= need) {
+      P::acquire_fence();
+      return true;
+    }
     if (P::load_relaxed(err) != 0u) return false;
     if ((int64_t)(P::now() - t0) > timeout_ticks) {
       P::raise(err);

@@ -27,8 +27,8 @@ using namespace stencil_impl;
 namespace {
 
 struct HostWait {
-  static unsigned load_acquire(const unsigned* p) { return __atomic_load_n(p, __ATOMIC_ACQUIRE); }
   static unsigned load_relaxed(const unsigned* p) { return __atomic_load_n(p, __ATOMIC_RELAXED); }
+  static void acquire_fence() { __atomic_thread_fence(__ATOMIC_ACQUIRE); }
   static void raise(unsigned* p) { __atomic_store_n(p, 1u, __ATOMIC_RELAXED); }
   static uint64_t now() {  // 100 MHz ticks, as the device's realtime clock
     return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
