@@ -135,6 +135,7 @@ KERNEL_SOURCES_3D = ("paper_2305_07390_amd/csrc/tb3d_impl.hpp",
                      "paper_2305_07390_amd/csrc/device_common.hpp")
 TRAFFIC_PROFILE_3D = "profiles/tb3d_traffic_3d_suite_512.md"
 KERNEL_SOURCES_BATCH = ("paper_2305_07390_amd/csrc/batch_impl.hpp",
+                        "paper_2305_07390_amd/csrc/worklist.hpp",
                         "paper_2305_07390_amd/csrc/tb2d_impl.hpp",
                         "paper_2305_07390_amd/csrc/tb3d_impl.hpp",
                         "paper_2305_07390_amd/csrc/device_common.hpp")
