@@ -50,11 +50,13 @@ def test_served_results_equal_alone(dtype, rounds):
         np.testing.assert_array_equal(got, _alone(prob, field, T))
 
 
-def test_burst_with_T0_and_naive_shapes():
+@pytest.mark.parametrize("rounds", [1, 2], ids=["one_round", "two_rounds"])
+def test_burst_with_T0_and_naive_shapes(rounds):
     spec = wl.SUITE_2D[1]
     coeffs = wl.coeffs_for(spec, 3)
     shapes = [(40, 50), (300, 520), (257, 1031)]  # the first has no blocked variant
-    with serving.Server(hbm_budget_bytes=1 << 30, max_slots=8, quantum_passes=1) as srv:
+    with serving.Server(hbm_budget_bytes=1 << 30, max_slots=8, quantum_passes=1,
+                        rounds_in_flight=rounds) as srv:
         tickets, fields = [], []
         for k, (shape, T) in enumerate(zip(shapes + shapes, [0, 7, 33, 5, 0, 19])):
             f = wl.make_field(shape, spec.r, seed=40 + k, dtype=np.float64)
@@ -118,7 +120,8 @@ def test_percentiles_match_latencies():
     assert s["cell_updates"] == sum(p.cells * T for p, _, T in reqs)
 
 
-def test_large_T0_request_returns_its_input():
+@pytest.mark.parametrize("rounds", [1, 2], ids=["one_round", "two_rounds"])
+def test_large_T0_request_returns_its_input(rounds):
     """A T = 0 request runs as a device copy in a round, ordered after its
     upload: a grid large enough that the upload takes a while comes back
     unchanged."""
@@ -126,7 +129,7 @@ def test_large_T0_request_returns_its_input():
     coeffs = wl.coeffs_for(spec, 3)
     f = wl.make_field((4096, 4096), 1, seed=71, dtype=np.float32)
     g = wl.make_field((300, 400), 1, seed=72, dtype=np.float32)
-    with serving.Server(hbm_budget_bytes=4 << 30, max_slots=4, quantum_passes=1) as srv:
+    with serving.Server(hbm_budget_bytes=4 << 30, max_slots=4, quantum_passes=1, rounds_in_flight=rounds) as srv:
         t0 = srv.submit(coeffs, 1, (4096, 4096), 0, f)
         t1 = srv.submit(coeffs, 1, (300, 400), 5, g)
         out0 = np.empty_like(f)
